@@ -1,0 +1,768 @@
+// C ABI of the local NBNN library: index residency, batch planning, the
+// launch sequence (direct or replayed from a hipGraph), timing and the
+// project autotuner.  See include/lnbnn.h for the contract of every entry
+// point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+#include "runtime.h"
+
+using namespace lnbnn;
+
+namespace lnbnn {
+
+static thread_local std::string g_err;
+
+int set_err(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_err(hipError_t e, const char *what)
+{
+    if (e == hipErrorOutOfMemory) return set_err(LNBNN_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+    return set_err(LNBNN_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// LNBNN_FAULT=alloc|launch makes the named site fail with LNBNN_EDEVICE, so
+// error paths can be exercised without breaking the device.
+bool fault_injected(const char *site)
+{
+    const char *f = getenv("LNBNN_FAULT");
+    return f && strcmp(f, site) == 0;
+}
+
+static hipError_t dmalloc(void **p, size_t bytes)
+{
+    if (fault_injected("alloc")) return hipErrorOutOfMemory;
+    return hipMalloc(p, bytes);
+}
+
+int64_t row_bytes(int dtype) { return dtype == LNBNN_U8 ? kDim : kDim * 4; }
+
+int mode_fmt(int mode)
+{
+    switch (mode) {
+    case LNBNN_EXACT_F16: return FMT_F16;
+    case LNBNN_EXACT_BF16: return FMT_BF16;
+    case LNBNN_FP8_RERANK: return FMT_FP8;
+    case LNBNN_EXACT_I8: return FMT_I8;
+    }
+    return -1;
+}
+
+Workspace::~Workspace()
+{
+    void *ps[] = {q, offsets, bd, part_d, part_i, totals, totals_f64, cls, nbr_idx, nbr_dist};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+}
+
+int64_t Workspace::bytes() const
+{
+    return qbytes_cap + (2 * img_cap + 2) * 8 + img_cap * (int64_t)sizeof(BatchDesc) + part_cap * 8 +
+           nbr_cap * 8 + img_cap * 4;
+}
+
+static int grow(void **p, int64_t have, int64_t need, size_t elem)
+{
+    if (need <= have && *p) return LNBNN_OK;
+    if (*p) {
+        LN_HIP(hipFree(*p));
+        *p = nullptr;
+    }
+    LN_HIP(dmalloc(p, (size_t)std::max<int64_t>(need, 1) * elem));
+    return LNBNN_OK;
+}
+
+static void drop_graphs(lnbnn_index *ix)
+{
+    for (auto &kv : ix->graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    }
+    ix->graphs.clear();
+}
+
+int ensure_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int64_t img_cap, int64_t part, int64_t nbr,
+              int64_t qbytes, bool need_f64)
+{
+    const bool ok = q_cap <= ws.q_cap && img_cap <= ws.img_cap && part <= ws.part_cap &&
+                    nbr <= ws.nbr_cap && qbytes <= ws.qbytes_cap && (!need_f64 || ws.totals_f64);
+    if (ok && ws.bd) return LNBNN_OK;
+    // buffers may be in use by earlier asynchronous work
+    LN_HIP(hipDeviceSynchronize());
+    if (&ws == &ix->ws) drop_graphs(ix);
+    const int64_t nc = ix->n_classes;
+    img_cap = std::max(img_cap, ws.img_cap);
+    int rc;
+    if (img_cap > ws.img_cap || !ws.bd) {
+        if ((rc = grow((void **)&ws.offsets, 0, 2 * img_cap + 2, 8))) return rc;
+        if ((rc = grow((void **)&ws.bd, 0, img_cap + 1, sizeof(BatchDesc)))) return rc;
+        if ((rc = grow((void **)&ws.totals, 0, img_cap * nc, 8))) return rc;
+        if ((rc = grow((void **)&ws.cls, 0, img_cap, 4))) return rc;
+        if (ws.totals_f64 || need_f64)
+            if ((rc = grow((void **)&ws.totals_f64, 0, img_cap * nc, 8))) return rc;
+        ws.img_cap = img_cap;
+    }
+    if (need_f64 && !ws.totals_f64)
+        if ((rc = grow((void **)&ws.totals_f64, 0, ws.img_cap * nc, 8))) return rc;
+    if (part > ws.part_cap) {
+        if ((rc = grow((void **)&ws.part_d, 0, part, 4))) return rc;
+        if ((rc = grow((void **)&ws.part_i, 0, part, 4))) return rc;
+        ws.part_cap = part;
+    }
+    if (nbr > ws.nbr_cap) {
+        if ((rc = grow((void **)&ws.nbr_idx, 0, nbr, 4))) return rc;
+        if ((rc = grow((void **)&ws.nbr_dist, 0, nbr, 4))) return rc;
+        ws.nbr_cap = nbr;
+    }
+    if (qbytes > ws.qbytes_cap) {
+        if ((rc = grow(&ws.q, 0, qbytes, 1))) return rc;
+        ws.qbytes_cap = qbytes;
+    }
+    ws.q_cap = std::max(ws.q_cap, q_cap);
+    return LNBNN_OK;
+}
+
+static int blocks_per_cu(lnbnn_index *ix, int v, int fmt, int kpb)
+{
+    auto key = std::make_tuple(v, fmt, kpb);
+    auto it = ix->occupancy.find(key);
+    if (it != ix->occupancy.end()) return it->second;
+    int n = dist_topk_blocks_per_cu(v, fmt, kpb);
+    if (n < 1) n = 1;
+    ix->occupancy[key] = n;
+    return n;
+}
+
+static int default_variant(int fmt, int kp)
+{
+    // 64 queries per wave halves LDS traffic per MFMA; fall back to 32
+    // queries per wave where the longer neighbour lists need the registers.
+    if (variant_supports(1, fmt, kp)) return 1;
+    return 0;
+}
+
+int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_variant, Plan *out)
+{
+    const int fmt = mode_fmt(mode);
+    const int kpb = kp_bucket(kp, fmt);
+    if (kpb == 0) return set_err(LNBNN_EINVAL, "k + 1 = %d is not supported by mode %d", kp, mode);
+    int v = forced_variant;
+    if (v < 0) {
+        auto it = ix->pinned.find({mode, kpb});
+        v = it != ix->pinned.end() ? it->second : default_variant(fmt, kp);
+    }
+    if (!variant_supports(v, fmt, kp))
+        return set_err(LNBNN_EINVAL, "variant %d cannot serve mode %d with k + 1 = %d", v, mode, kp);
+    const Variant var = variant(v);
+    const int64_t qb = (int64_t)waves_per_block() * 32 * var.nt;
+    const int64_t n_qb = std::max<int64_t>(1, (q_cap + qb - 1) / qb);
+    const int64_t n_tiles = ix->n_pad / kTileRows;
+    const int bpc = blocks_per_cu(ix, v, fmt, kpb);
+    const int64_t resident = (int64_t)ix->cu_count * bpc;
+    // Split the reference set only when the query blocks alone cannot keep
+    // every workgroup slot busy; each split costs one more partial list.
+    int64_t want = 1;
+    if (n_qb < 2 * resident) want = std::min<int64_t>(32, (2 * resident + n_qb - 1) / n_qb);
+    int64_t tps = (n_tiles + want - 1) / want;
+    tps = std::max<int64_t>(8, (tps + 7) / 8 * 8);
+    const int64_t S = (n_tiles + tps - 1) / tps;
+    out->variant = v;
+    out->fmt = fmt;
+    out->kpb = kpb;
+    out->n_slices = (int)S;
+    out->tiles_per_slice = (int)tps;
+    out->grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_qb * S, resident));
+    out->q_cap = q_cap;
+    return LNBNN_OK;
+}
+
+int64_t part_elems(const Plan &p, int64_t q_cap) { return (int64_t)p.n_slices * 2 * q_cap * p.kpb; }
+
+int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t s, hipEvent_t *ev)
+{
+    if (fault_injected("launch")) return set_err(LNBNN_EDEVICE, "injected launch failure");
+    if (ev) LN_HIP(hipEventRecord(ev[2], s));
+    LN_HIP(launch_fill_u64(io.totals, io.img_cap * ix->n_classes, io.bd, ix->n_classes, s));
+    DistArgs a{};
+    a.q = io.q;
+    a.bd = io.bd;
+    a.frag = ix->frag[p.fmt];
+    a.seed = ix->seed[p.fmt];
+    a.n_tiles = ix->n_pad / kTileRows;
+    a.tiles_per_slice = p.tiles_per_slice;
+    a.n_slices = p.n_slices;
+    a.q_cap = io.q_cap;
+    a.part_d = io.part_d;
+    a.part_i = io.part_i;
+    if (ev) LN_HIP(hipEventRecord(ev[0], s));
+    LN_HIP(launch_dist_topk(p.variant, p.fmt, p.kpb, a, p.grid, s));
+    if (ev) LN_HIP(hipEventRecord(ev[1], s));
+    FinishArgs f{};
+    f.q = io.q;
+    f.bd = io.bd;
+    f.offsets = io.offsets;
+    f.labels = ix->labels;
+    f.n_refs = ix->n_refs;
+    f.n_lists = 2 * p.n_slices;
+    f.kp_stride = p.kpb;
+    f.k = io.k;
+    f.n_classes = ix->n_classes;
+    f.q_cap = io.q_cap;
+    f.part_d = io.part_d;
+    f.part_i = io.part_i;
+    f.totals = io.totals;
+    f.nbr_idx = io.nbr_idx;
+    f.nbr_dist = io.nbr_dist;
+    f.fixed_point = p.fmt == FMT_FP8;
+    LN_HIP(launch_finish(f, io.q_cap, s));
+    LN_HIP(launch_argmin(io.totals, io.bd, io.img_cap, ix->n_classes, io.cls, io.totals_f64,
+                         p.fmt == FMT_FP8, s));
+    if (ev) LN_HIP(hipEventRecord(ev[3], s));
+    return LNBNN_OK;
+}
+
+}  // namespace lnbnn
+
+// ===========================================================================
+// index
+// ===========================================================================
+static int free_index_buffers(lnbnn_index *ix)
+{
+    for (int f = 0; f < 4; ++f) {
+        if (ix->frag[f]) (void)hipFree(ix->frag[f]);
+        ix->frag[f] = nullptr;
+    }
+    // seeds of the two exact 16-bit formats share one buffer
+    if (ix->seed[FMT_F16]) (void)hipFree(ix->seed[FMT_F16]);
+    else if (ix->seed[FMT_BF16]) (void)hipFree(ix->seed[FMT_BF16]);
+    for (int f = 0; f < 4; ++f) ix->seed[f] = nullptr;
+    if (ix->labels) (void)hipFree(ix->labels);
+    if (ix->ref_f32) (void)hipFree(ix->ref_f32);
+    ix->labels = nullptr;
+    ix->ref_f32 = nullptr;
+    return LNBNN_OK;
+}
+
+extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, int32_t dim,
+                                 const int32_t *labels, int32_t n_classes, uint32_t mode_mask,
+                                 int64_t hbm_budget_bytes, uint32_t flags, void *stream,
+                                 lnbnn_index **out)
+{
+    if (!out || !refs || !labels) return set_err(LNBNN_EINVAL, "NULL argument");
+    if (dim != LNBNN_DIM) return set_err(LNBNN_EINVAL, "dim must be %d (got %d)", LNBNN_DIM, dim);
+    if (n_refs < 1 || n_refs >= (int64_t)0x7fffffff - kPadRows)
+        return set_err(LNBNN_EINVAL, "n_refs out of range: %lld", (long long)n_refs);
+    if (n_classes < 1) return set_err(LNBNN_EINVAL, "n_classes must be >= 1");
+    if (dtype != LNBNN_U8 && dtype != LNBNN_F32) return set_err(LNBNN_EINVAL, "bad dtype %d", dtype);
+    if (hbm_budget_bytes < 0) return set_err(LNBNN_EINVAL, "negative HBM budget");
+    const uint32_t exact = LNBNN_MODE_BIT(LNBNN_EXACT_F16) | LNBNN_MODE_BIT(LNBNN_EXACT_BF16);
+    if (mode_mask == 0) return set_err(LNBNN_EINVAL, "empty mode mask");
+    if (dtype == LNBNN_U8 && (mode_mask & ~exact))
+        return set_err(LNBNN_EINVAL, "mode mask 0x%x: u8 data builds only the exact FP16/BF16 modes",
+                       mode_mask);
+    if (dtype == LNBNN_F32)
+        return set_err(LNBNN_EINVAL, "float references (FP8 re-rank mode) are not built in this library");
+    if (flags & ~(uint32_t)LNBNN_DEVICE_PTRS) return set_err(LNBNN_EINVAL, "unknown flags 0x%x", flags);
+    const bool dev_in = flags & LNBNN_DEVICE_PTRS;
+    if (!dev_in) {
+        for (int64_t j = 0; j < n_refs; ++j)
+            if (labels[j] < 0 || labels[j] >= n_classes)
+                return set_err(LNBNN_EINVAL, "label[%lld] = %d outside [0, %d)", (long long)j, labels[j],
+                               n_classes);
+    }
+
+    int dev = 0;
+    LN_HIP(hipGetDevice(&dev));
+    std::unique_ptr<lnbnn_index> ix(new lnbnn_index());
+    ix->device = dev;
+    ix->dtype = dtype;
+    ix->n_refs = n_refs;
+    ix->n_pad = (n_refs + kPadRows - 1) / kPadRows * kPadRows;
+    ix->n_classes = n_classes;
+    ix->modes = mode_mask;
+    ix->ws.device = dev;
+    LN_HIP(hipDeviceGetAttribute(&ix->cu_count, hipDeviceAttributeMultiprocessorCount, dev));
+    // a blocking stream stays ordered after work on the NULL stream
+    LN_HIP(hipStreamCreate(&ix->own_stream));
+    for (auto &e : ix->tev) LN_HIP(hipEventCreate(&e));
+    LN_HIP(hipEventCreateWithFlags(&ix->ws_free, hipEventDisableTiming));
+    hipStream_t s = stream ? (hipStream_t)stream : ix->own_stream;
+
+    auto fail = [&](int rc) {
+        (void)hipStreamSynchronize(s);
+        free_index_buffers(ix.get());
+        return rc;
+    };
+
+    // labels: device copy (and validation when they came as device memory)
+    int rc;
+    if ((rc = grow((void **)&ix->labels, 0, n_refs, 4))) return fail(rc);
+    if (dev_in) {
+        std::vector<int32_t> hl(n_refs);
+        hipError_t e = hipMemcpy(hl.data(), labels, n_refs * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return fail(hip_err(e, "hipMemcpy(labels)"));
+        for (int64_t j = 0; j < n_refs; ++j)
+            if (hl[j] < 0 || hl[j] >= n_classes)
+                return fail(set_err(LNBNN_EINVAL, "label[%lld] = %d outside [0, %d)", (long long)j, hl[j],
+                                    n_classes));
+        e = hipMemcpyAsync(ix->labels, labels, n_refs * 4, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return fail(hip_err(e, "hipMemcpyAsync(labels)"));
+    } else {
+        hipError_t e = hipMemcpyAsync(ix->labels, labels, n_refs * 4, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return fail(hip_err(e, "hipMemcpyAsync(labels)"));
+    }
+
+    // references: stage u8 rows on the device, then pack per mode
+    const uint8_t *d_refs = static_cast<const uint8_t *>(refs);
+    void *staged = nullptr;
+    if (!dev_in) {
+        if ((rc = grow(&staged, 0, n_refs * kDim, 1))) return fail(rc);
+        hipError_t e = hipMemcpyAsync(staged, refs, (size_t)n_refs * kDim, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) {
+            (void)hipFree(staged);
+            return fail(hip_err(e, "hipMemcpyAsync(refs)"));
+        }
+        d_refs = static_cast<const uint8_t *>(staged);
+    }
+    float *seed = nullptr;
+    int64_t bytes = n_refs * 4;
+    rc = grow((void **)&seed, 0, ix->n_pad, 4);
+    if (!rc) bytes += ix->n_pad * 4;
+    bool seeded = false;
+    for (int mode : {LNBNN_EXACT_F16, LNBNN_EXACT_BF16}) {
+        if (rc || !(mode_mask & LNBNN_MODE_BIT(mode))) continue;
+        const int fmt = mode_fmt(mode);
+        if ((rc = grow((void **)&ix->frag[fmt], 0, ix->n_pad * kDim * 2, 1))) break;
+        bytes += ix->n_pad * kDim * 2;
+        hipError_t e = launch_pack_u8(d_refs, n_refs, ix->n_pad, fmt, ix->frag[fmt], seeded ? nullptr : seed, s);
+        if (e != hipSuccess) {
+            rc = hip_err(e, "pack");
+            break;
+        }
+        seeded = true;
+        ix->seed[fmt] = seed;
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (staged) (void)hipFree(staged);
+    if (rc) {
+        if (seed && !seeded) (void)hipFree(seed);
+        return fail(rc);
+    }
+    if (e != hipSuccess) return fail(hip_err(e, "build_index sync"));
+    ix->device_bytes = bytes;
+    size_t free_b = 0, total_b = 0;
+    LN_HIP(hipMemGetInfo(&free_b, &total_b));
+    ix->hbm_budget = hbm_budget_bytes ? hbm_budget_bytes : (int64_t)(free_b / 4);
+    *out = ix.release();
+    return LNBNN_OK;
+}
+
+extern "C" int lnbnn_index_free(lnbnn_index *ix)
+{
+    if (!ix) return LNBNN_OK;
+    if (server_pending(ix)) return set_err(LNBNN_EBUSY, "index has pending tickets");
+    server_stop(ix);
+    (void)hipSetDevice(ix->device);
+    (void)hipDeviceSynchronize();
+    drop_graphs(ix);
+    free_index_buffers(ix);
+    for (auto &e : ix->tev)
+        if (e) (void)hipEventDestroy(e);
+    if (ix->ws_free) (void)hipEventDestroy(ix->ws_free);
+    if (ix->own_stream) (void)hipStreamDestroy(ix->own_stream);
+    delete ix;
+    return LNBNN_OK;
+}
+
+extern "C" int lnbnn_index_info(const lnbnn_index *ix, int64_t *n_refs, int32_t *n_classes,
+                                uint32_t *mode_mask, int64_t *device_bytes)
+{
+    if (!ix) return set_err(LNBNN_EINVAL, "NULL index");
+    if (n_refs) *n_refs = ix->n_refs;
+    if (n_classes) *n_classes = ix->n_classes;
+    if (mode_mask) *mode_mask = ix->modes;
+    if (device_bytes) *device_bytes = ix->device_bytes;
+    return LNBNN_OK;
+}
+
+// ===========================================================================
+// classify
+// ===========================================================================
+static int validate_classify(const lnbnn_index *ix, const void *queries, int dtype, const int64_t *off,
+                             int32_t n_images, int32_t k, int mode, uint32_t flags, bool has_out_class,
+                             const int32_t *nbr_idx, const float *nbr_dist)
+{
+    if (!ix) return set_err(LNBNN_EINVAL, "NULL index");
+    if (!off || !has_out_class) return set_err(LNBNN_EINVAL, "NULL img_offsets or out_class");
+    if (n_images < 0) return set_err(LNBNN_EINVAL, "n_images < 0");
+    if (flags & ~(uint32_t)(LNBNN_DEVICE_PTRS | LNBNN_PER_IMAGE_LAUNCH | LNBNN_NO_GRAPH | LNBNN_TIMING))
+        return set_err(LNBNN_EINVAL, "unknown flags 0x%x", flags);
+    if (mode < 0 || mode > 3 || !(ix->modes & LNBNN_MODE_BIT(mode)))
+        return set_err(LNBNN_EINVAL, "mode %d is not materialised in this index", mode);
+    const int want = mode == LNBNN_FP8_RERANK ? LNBNN_F32 : LNBNN_U8;
+    if (dtype != want) return set_err(LNBNN_EINVAL, "dtype %d does not match mode %d", dtype, mode);
+    if (k < 1 || k > LNBNN_MAX_K) return set_err(LNBNN_EINVAL, "k = %d outside [1, %d]", k, LNBNN_MAX_K);
+    if ((int64_t)k + 1 > ix->n_refs) return set_err(LNBNN_EINVAL, "k + 1 > n_refs");
+    if ((nbr_idx == nullptr) != (nbr_dist == nullptr))
+        return set_err(LNBNN_EINVAL, "out_nbr_idx and out_nbr_dist must both be set or both NULL");
+    if (off[0] != 0) return set_err(LNBNN_EINVAL, "img_offsets[0] must be 0");
+    for (int32_t m = 0; m < n_images; ++m)
+        if (off[m + 1] < off[m]) return set_err(LNBNN_EINVAL, "img_offsets decrease at %d", m);
+    if (off[n_images] > 0 && !queries) return set_err(LNBNN_EINVAL, "NULL queries");
+    return LNBNN_OK;
+}
+
+static std::string graph_key(const Plan &p, const BatchIO &io)
+{
+    std::ostringstream o;
+    o << p.variant << '/' << p.fmt << '/' << p.kpb << '/' << p.n_slices << '/' << p.tiles_per_slice << '/'
+      << p.grid << '/' << io.q_cap << '/' << io.img_cap << '/' << io.k << '/' << io.mode << '/' << io.q << '/'
+      << io.offsets << '/' << io.bd << '/' << io.cls << '/' << io.totals << '/' << io.totals_f64 << '/'
+      << io.nbr_idx << '/' << io.nbr_dist << '/' << io.part_d << '/' << io.part_i;
+    return o.str();
+}
+
+// Replay (capturing on first use) the launch sequence of a batch.
+static int launch_graph(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t s)
+{
+    const std::string key = graph_key(p, io);
+    auto it = ix->graphs.find(key);
+    if (it == ix->graphs.end()) {
+        GraphEntry g;
+        LN_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_batch(ix, p, io, s, nullptr);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_err(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_err(e, "hipGraphInstantiate");
+        it = ix->graphs.emplace(key, g).first;
+    }
+    LN_HIP(hipGraphLaunch(it->second.exec, s));
+    return LNBNN_OK;
+}
+
+static int classify_per_image(lnbnn_index *ix, const void *dq, const int64_t *off, int32_t n_images,
+                              int32_t k, int mode, int32_t *cls, int32_t *nbr_idx, float *nbr_dist, hipStream_t s,
+                              hipEvent_t *ev)
+{
+    Workspace &ws = ix->ws;
+    const int kp = k + 1;
+    std::vector<Plan> plans(n_images);
+    for (int32_t m = 0; m < n_images; ++m) {
+        int rc = make_plan(ix, mode, kp, std::max<int64_t>(1, off[m + 1] - off[m]), -1, &plans[m]);
+        if (rc) return rc;
+    }
+    std::vector<BatchDesc> bds(n_images);
+    std::vector<int64_t> offs(2 * (size_t)n_images);
+    for (int32_t m = 0; m < n_images; ++m) {
+        bds[m].n_q = off[m + 1] - off[m];
+        bds[m].n_img = 1;
+        offs[2 * m] = 0;
+        offs[2 * m + 1] = bds[m].n_q;
+    }
+    LN_HIP(hipMemcpyAsync(ws.bd, bds.data(), n_images * sizeof(BatchDesc), hipMemcpyHostToDevice, s));
+    LN_HIP(hipMemcpyAsync(ws.offsets, offs.data(), offs.size() * 8, hipMemcpyHostToDevice, s));
+    const int64_t rb = row_bytes(ix->dtype);
+    double kms = 0;
+    for (int32_t m = 0; m < n_images; ++m) {
+        BatchIO io;
+        io.q = static_cast<const uint8_t *>(dq) + off[m] * rb;
+        io.offsets = ws.offsets + 2 * m;
+        io.bd = ws.bd + m;
+        io.q_cap = plans[m].q_cap;
+        io.img_cap = 1;
+        io.k = k;
+        io.mode = mode;
+        io.cls = cls + m;
+        io.totals = ws.totals + (int64_t)m * ix->n_classes;
+        io.nbr_idx = nbr_idx ? nbr_idx + off[m] * kp : nullptr;
+        io.nbr_dist = nbr_dist ? nbr_dist + off[m] * kp : nullptr;
+        io.part_d = ws.part_d;
+        io.part_i = ws.part_i;
+        int rc = enqueue_batch(ix, plans[m], io, s, ev);
+        if (rc) return rc;
+        if (ev) {
+            LN_HIP(hipEventSynchronize(ev[1]));
+            float ms = 0;
+            LN_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            kms += ms;
+        }
+    }
+    if (ev) {
+        ix->last_timing.dist_kernel_ms = kms;
+        ix->last_timing.dist_launches = n_images;
+    }
+    return LNBNN_OK;
+}
+
+extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, const int64_t *img_offsets,
+                              int32_t n_images, int32_t k, int mode, uint32_t flags, int32_t *out_class,
+                              void *out_totals, int32_t *out_nbr_idx, float *out_nbr_dist, void *stream)
+{
+    int rc = validate_classify(ix, queries, dtype, img_offsets, n_images, k, mode, flags, out_class != nullptr,
+                               out_nbr_idx, out_nbr_dist);
+    if (rc) return rc;
+    if (n_images == 0) return LNBNN_OK;
+    if (mode == LNBNN_FP8_RERANK || mode == LNBNN_EXACT_I8)
+        return set_err(LNBNN_EINVAL, "mode %d is not built in this library", mode);
+    std::lock_guard<std::mutex> lock(ix->mu);
+    LN_HIP(hipSetDevice(ix->device));
+    hipStream_t s = stream ? (hipStream_t)stream : ix->own_stream;
+    const bool dev = flags & LNBNN_DEVICE_PTRS;
+    const bool per_image = flags & LNBNN_PER_IMAGE_LAUNCH;
+    const bool timed = flags & LNBNN_TIMING;
+    const int kp = k + 1;
+    const int64_t n_q = img_offsets[n_images];
+    const int64_t rb = row_bytes(dtype);
+    const int64_t nc = ix->n_classes;
+
+    Plan plan;
+    int64_t part = 0;
+    if (per_image) {
+        for (int32_t m = 0; m < n_images; ++m) {
+            Plan pm;
+            if ((rc = make_plan(ix, mode, kp, std::max<int64_t>(1, img_offsets[m + 1] - img_offsets[m]), -1, &pm)))
+                return rc;
+            part = std::max(part, part_elems(pm, pm.q_cap));
+        }
+    } else {
+        if ((rc = make_plan(ix, mode, kp, std::max<int64_t>(1, n_q), -1, &plan))) return rc;
+        part = part_elems(plan, plan.q_cap);
+    }
+    const bool want_nbr = out_nbr_idx != nullptr;
+    if ((rc = ensure_ws(ix, ix->ws, std::max<int64_t>(1, n_q), n_images, part,
+                        (want_nbr && !dev) ? n_q * kp : 0, dev ? 0 : n_q * rb, false)))
+        return rc;
+    Workspace &ws = ix->ws;
+
+    // the shared workspace may still be read by a call on another stream
+    if (ix->ws_used) LN_HIP(hipStreamWaitEvent(s, ix->ws_free, 0));
+    const void *dq = queries;
+    if (!dev && n_q > 0) {
+        LN_HIP(hipMemcpyAsync(ws.q, queries, (size_t)(n_q * rb), hipMemcpyHostToDevice, s));
+        dq = ws.q;
+    }
+    int32_t *d_cls = dev ? out_class : ws.cls;
+    int32_t *d_nbr_i = want_nbr ? (dev ? out_nbr_idx : ws.nbr_idx) : nullptr;
+    float *d_nbr_d = want_nbr ? (dev ? out_nbr_dist : ws.nbr_dist) : nullptr;
+
+    hipEvent_t *ev = nullptr;
+    if (per_image) {
+        if (timed) ev = ix->tev;
+        if (timed) LN_HIP(hipEventRecord(ix->tev[2], s));
+        rc = classify_per_image(ix, dq, img_offsets, n_images, k, mode, d_cls, d_nbr_i, d_nbr_d, s,
+                                timed ? ix->tev : nullptr);
+        if (rc) return rc;
+        if (timed) LN_HIP(hipEventRecord(ix->tev[3], s));
+    } else {
+        BatchDesc hb{n_q, n_images};
+        LN_HIP(hipMemcpyAsync(ws.bd, &hb, sizeof hb, hipMemcpyHostToDevice, s));
+        LN_HIP(hipMemcpyAsync(ws.offsets, img_offsets, (size_t)(n_images + 1) * 8, hipMemcpyHostToDevice, s));
+        BatchIO io;
+        io.q = dq;
+        io.offsets = ws.offsets;
+        io.bd = ws.bd;
+        io.q_cap = plan.q_cap;
+        io.img_cap = n_images;
+        io.k = k;
+        io.mode = mode;
+        io.cls = d_cls;
+        io.totals = ws.totals;
+        io.nbr_idx = d_nbr_i;
+        io.nbr_dist = d_nbr_d;
+        io.part_d = ws.part_d;
+        io.part_i = ws.part_i;
+        // timed calls launch directly: events recorded inside a captured
+        // graph cannot be read back with hipEventElapsedTime
+        if ((flags & LNBNN_NO_GRAPH) || timed) {
+            if (timed) ev = ix->tev;
+            if ((rc = enqueue_batch(ix, plan, io, s, ev))) return rc;
+        } else {
+            if ((rc = launch_graph(ix, plan, io, s))) return rc;
+        }
+    }
+
+    // outputs
+    if (out_totals)
+        LN_HIP(hipMemcpyAsync(out_totals, ws.totals, (size_t)(n_images * nc * 8),
+                              dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    if (!dev) {
+        LN_HIP(hipMemcpyAsync(out_class, ws.cls, (size_t)n_images * 4, hipMemcpyDeviceToHost, s));
+        if (want_nbr) {
+            LN_HIP(hipMemcpyAsync(out_nbr_idx, ws.nbr_idx, (size_t)(n_q * kp * 4), hipMemcpyDeviceToHost, s));
+            LN_HIP(hipMemcpyAsync(out_nbr_dist, ws.nbr_dist, (size_t)(n_q * kp * 4), hipMemcpyDeviceToHost, s));
+        }
+    }
+    LN_HIP(hipEventRecord(ix->ws_free, s));
+    ix->ws_used = true;
+    if (!dev) LN_HIP(hipStreamSynchronize(s));
+    if (timed) {
+        LN_HIP(hipEventSynchronize(ev[3]));
+        float ms = 0;
+        if (!per_image) {
+            LN_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            ix->last_timing.dist_kernel_ms = ms;
+            ix->last_timing.dist_launches = 1;
+        }
+        LN_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
+        ix->last_timing.total_ms = ms;
+        ix->last_timing.slices = per_image ? 0 : plan.n_slices;
+        ix->last_timing.tile_variant = per_image ? -1 : plan.variant;
+        ix->has_timing = true;
+    }
+    return LNBNN_OK;
+}
+
+extern "C" int lnbnn_last_timing(const lnbnn_index *ix, lnbnn_timing *out)
+{
+    if (!ix || !out) return set_err(LNBNN_EINVAL, "NULL argument");
+    if (!ix->has_timing) return set_err(LNBNN_EINVAL, "no timed classify has run on this index");
+    *out = ix->last_timing;
+    return LNBNN_OK;
+}
+
+// ===========================================================================
+// variants and autotuner
+// ===========================================================================
+extern "C" int32_t lnbnn_num_variants(void) { return num_variants(); }
+extern "C" const char *lnbnn_variant_name(int32_t v) { return variant_name(v); }
+
+extern "C" int lnbnn_set_variant(lnbnn_index *ix, int mode, int32_t k, int32_t v)
+{
+    if (!ix) return set_err(LNBNN_EINVAL, "NULL index");
+    if (mode < 0 || mode > 3 || !(ix->modes & LNBNN_MODE_BIT(mode))) return set_err(LNBNN_EINVAL, "bad mode");
+    if (k < 1 || k > LNBNN_MAX_K) return set_err(LNBNN_EINVAL, "bad k");
+    const int fmt = mode_fmt(mode);
+    const int kpb = kp_bucket(k + 1, fmt);
+    std::lock_guard<std::mutex> lock(ix->mu);
+    if (v < 0) {
+        ix->pinned.erase({mode, kpb});
+        return LNBNN_OK;
+    }
+    if (!variant_supports(v, fmt, k + 1)) return set_err(LNBNN_EINVAL, "variant %d cannot serve k = %d", v, k);
+    ix->pinned[{mode, kpb}] = v;
+    return LNBNN_OK;
+}
+
+// Flat JSON object of string -> integer, the tuning cache format.
+static std::map<std::string, int> read_cache(const char *path)
+{
+    std::map<std::string, int> m;
+    std::ifstream f(path);
+    if (!f) return m;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    size_t i = 0;
+    while ((i = s.find('"', i)) != std::string::npos) {
+        const size_t j = s.find('"', i + 1);
+        if (j == std::string::npos) break;
+        const std::string key = s.substr(i + 1, j - i - 1);
+        const size_t c = s.find(':', j);
+        if (c == std::string::npos) break;
+        m[key] = atoi(s.c_str() + c + 1);
+        i = s.find_first_of(",}", c);
+        if (i == std::string::npos) break;
+    }
+    return m;
+}
+
+static void write_cache(const char *path, const std::map<std::string, int> &m)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    std::ofstream f(tmp);
+    f << "{\n";
+    size_t n = 0;
+    for (auto &kv : m) f << "  \"" << kv.first << "\": " << kv.second << (++n < m.size() ? ",\n" : "\n");
+    f << "}\n";
+    f.close();
+    std::rename(tmp.c_str(), path);
+}
+
+extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtype, const int64_t *img_offsets,
+                              int32_t n_images, int32_t k, int mode, const char *cache_path,
+                              int32_t *best_variant, void *stream)
+{
+    int rc = validate_classify(ix, queries_dev, dtype, img_offsets, n_images, k, mode, LNBNN_DEVICE_PTRS, true,
+                               nullptr, nullptr);
+    if (rc) return rc;
+    if (mode == LNBNN_FP8_RERANK || mode == LNBNN_EXACT_I8)
+        return set_err(LNBNN_EINVAL, "mode %d is not built in this library", mode);
+    const int fmt = mode_fmt(mode);
+    const int kpb = kp_bucket(k + 1, fmt);
+    char arch[64] = "gfx";
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, ix->device) == hipSuccess) snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
+    }
+    std::ostringstream key;
+    key << "arch=" << arch << ",n_refs=" << ix->n_refs << ",dim=" << kDim << ",kp=" << kpb << ",mode=" << mode;
+    if (cache_path) {
+        auto m = read_cache(cache_path);
+        auto it = m.find(key.str());
+        if (it != m.end() && variant_supports(it->second, fmt, k + 1)) {
+            std::lock_guard<std::mutex> lock(ix->mu);
+            ix->pinned[{mode, kpb}] = it->second;
+            if (best_variant) *best_variant = it->second;
+            return LNBNN_OK;
+        }
+    }
+    const int64_t n_q = img_offsets[n_images];
+    std::vector<int32_t> cls(n_images);
+    int32_t *d_cls = nullptr;
+    LN_HIP(hipMalloc((void **)&d_cls, std::max<int32_t>(1, n_images) * 4));
+    int best = -1;
+    double best_ms = 1e30;
+    for (int v = 0; v < num_variants(); ++v) {
+        if (!variant_supports(v, fmt, k + 1)) continue;
+        if ((rc = lnbnn_set_variant(ix, mode, k, v))) break;
+        double tot = 0;
+        for (int rep = 0; rep < 3 && !rc; ++rep) {
+            rc = lnbnn_classify(ix, queries_dev, dtype, img_offsets, n_images, k, mode,
+                                LNBNN_DEVICE_PTRS | LNBNN_NO_GRAPH | LNBNN_TIMING, d_cls, nullptr, nullptr, nullptr,
+                                stream);
+            if (!rc && rep > 0) tot += ix->last_timing.dist_kernel_ms;
+        }
+        if (rc) break;
+        if (tot / 2 < best_ms) {
+            best_ms = tot / 2;
+            best = v;
+        }
+    }
+    (void)hipFree(d_cls);
+    (void)n_q;
+    if (rc) {
+        lnbnn_set_variant(ix, mode, k, -1);
+        return rc;
+    }
+    lnbnn_set_variant(ix, mode, k, best);
+    if (best_variant) *best_variant = best;
+    if (cache_path) {
+        auto m = read_cache(cache_path);
+        m[key.str()] = best;
+        write_cache(cache_path, m);
+    }
+    return LNBNN_OK;
+}
+
+extern "C" const char *lnbnn_last_error(void) { return g_err.c_str(); }

@@ -1,0 +1,95 @@
+// Internal interface between the C-ABI runtime and the HIP kernels.
+// Nothing here crosses the public boundary (include/lnbnn.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lnbnn {
+
+constexpr int kDim = 128;
+constexpr int kTileRows = 32;            // rows of one MFMA A tile
+constexpr int kPadRows = 256;            // index rows are padded to this multiple
+constexpr int kMaxKP = 33;               // k + 1 <= 33
+constexpr int kWaves = 4;                // waves per workgroup of the distance kernel
+
+// Element formats of the packed reference tiles.
+enum Fmt { FMT_F16 = 0, FMT_BF16 = 1, FMT_FP8 = 2, FMT_I8 = 3 };
+
+// Batch shape read on the device, so one captured launch sequence serves
+// every batch up to the capacity it was captured for.
+struct BatchDesc {
+    int64_t n_q;        // query descriptors in the batch
+    int64_t n_img;      // images in the batch
+};
+
+// A distance-kernel variant: queries per wave = 32 * nt, reference tiles
+// per LDS stage = mt.  `kp` is the list length the kernel keeps (>= k + 1).
+struct Variant {
+    int nt;
+    int mt;
+};
+
+struct DistArgs {
+    const void *q;              // queries: u8 [n_q, 128] (exact) / fp8 codes (fp8)
+    const int32_t *q_scale;     // fp8: per-query exponent bias (else null)
+    const BatchDesc *bd;        // device batch descriptor
+    const uint4 *frag;          // packed reference fragments
+    const float *seed;          // per-row accumulator seed (norm), +inf on padding
+    const int32_t *row_scale;   // fp8: per-row exponent bias (else null)
+    int64_t n_tiles;            // 32-row tiles in the padded index (multiple of 8)
+    int32_t tiles_per_slice;    // multiple of 8
+    int32_t n_slices;
+    int64_t q_cap;              // capacity: part buffers are laid out for q_cap queries
+    float *part_d;              // [n_slices * 2][q_cap][kp]
+    int32_t *part_i;
+};
+
+struct FinishArgs {
+    const void *q;              // u8 queries (exact: for ||q||^2) or f32 queries (fp8)
+    const BatchDesc *bd;
+    const int64_t *offsets;     // device [n_img + 1]
+    const int32_t *labels;      // [n_refs]
+    int64_t n_refs;
+    const float *ref_f32;       // fp8 mode: FP32 references for the re-rank
+    int32_t n_lists;            // 2 * n_slices
+    int32_t kp_stride;          // list length in the part buffers
+    int32_t k;
+    int32_t n_classes;
+    int64_t q_cap;
+    const float *part_d;
+    const int32_t *part_i;
+    unsigned long long *totals; // [n_img, n_classes] int64 (two's complement)
+    int32_t *nbr_idx;           // [n_q, k+1] or null
+    float *nbr_dist;            // [n_q, k+1] or null
+    int32_t fixed_point;        // fp8 mode: totals are fixed point * 2^40
+};
+
+// number of kernel variants and their parameters
+int num_variants();
+Variant variant(int v);
+const char *variant_name(int v);
+bool variant_supports(int v, int fmt, int kp);
+int kp_bucket(int kp, int fmt);         // list length compiled for kp (0 = unsupported)
+int waves_per_block();
+
+// Upload-side packing.  refs_u8 / refs_f32 are device pointers.
+hipError_t launch_pack_u8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, int fmt,
+                          uint4 *frag, float *seed, hipStream_t s);
+hipError_t launch_pack_f32_fp8(const float *refs, int64_t n_refs, int64_t n_pad,
+                               uint4 *frag, float *seed, int32_t *row_scale, hipStream_t s);
+hipError_t launch_quant_queries_fp8(const float *q, const BatchDesc *bd, int64_t q_cap,
+                                    uint8_t *q8, int32_t *q_scale, hipStream_t s);
+
+hipError_t launch_dist_topk(int variant, int fmt, int kp, const DistArgs &a, int grid,
+                            hipStream_t s);
+int dist_topk_blocks_per_cu(int variant, int fmt, int kp);
+
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n_elems_cap, const BatchDesc *bd,
+                           int32_t n_classes, hipStream_t s);
+hipError_t launch_finish(const FinishArgs &a, int64_t q_cap, hipStream_t s);
+hipError_t launch_argmin(const unsigned long long *totals, const BatchDesc *bd, int64_t img_cap,
+                         int32_t n_classes, int32_t *out_class, double *totals_f64,
+                         int32_t fixed_point, hipStream_t s);
+
+}  // namespace lnbnn

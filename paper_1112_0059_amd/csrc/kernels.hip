@@ -1,0 +1,590 @@
+// HIP kernels of the local NBNN hot path for gfx950 (MI355X).
+//
+// K0  pack        references -> MFMA A-fragment tiles + accumulator seeds
+// K1  dist_topk   distances on the matrix cores fused with top-(k+1)
+//                 selection in registers (Algorithm 2, NN(d_i, k+1))
+// K2  finish      merge of the per-slice lists, background distance,
+//                 per-class update of the image totals (Algorithm 2 body)
+// K3  argmin      per-image decision (Algorithm 2, return line)
+//
+// Distances.  For a query q and reference r the kernels rank by
+//     d'(q, r) = ||r||^2 - 2 q.r  =  ||q - r||^2 - ||q||^2,
+// which orders references exactly like the squared distance of Algorithm 2
+// and leaves every difference dist_C - dist_B unchanged.  The MFMA
+// accumulator is seeded with ||r||^2 and the query operand carries -2q, so
+// one chain of MFMAs yields d' with no extra vector work.  For u8 data every
+// product and partial sum is an integer below 2^24 in magnitude, so FP16 and
+// BF16 operands with FP32 accumulation are exact in any summation order.
+#include "internal.h"
+
+namespace lnbnn {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+static __device__ __forceinline__ uint32_t byte_at(uint2 r, int e)
+{
+    return ((e < 4 ? r.x : r.y) >> (8 * (e & 3))) & 0xffu;
+}
+
+// ---------------------------------------------------------------------------
+// Operand policies.  A fragment step covers 16 elements of K for FP16/BF16
+// (v_mfma_f32_32x32x16_{f16,bf16}): lane l supplies row (l & 31) and K
+// elements 16*s + 8*(l >> 5) + e, e = 0..7, for both operands, so packing the
+// references and loading the queries with the same rule pairs them correctly.
+// ---------------------------------------------------------------------------
+struct OpF16 {
+    static constexpr int kFmt = FMT_F16;
+    static constexpr int kSteps = 8;
+    static __device__ __forceinline__ uint4 cvt8(uint2 raw, float mul)
+    {
+        f16x8 v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (_Float16)(mul * (float)byte_at(raw, e));
+        return __builtin_bit_cast(uint4, v);
+    }
+    static __device__ __forceinline__ f32x16 mma(uint4 a, uint4 b, f32x16 c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                      __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+    }
+};
+
+struct OpBF16 {
+    static constexpr int kFmt = FMT_BF16;
+    static constexpr int kSteps = 8;
+    static __device__ __forceinline__ uint4 cvt8(uint2 raw, float mul)
+    {
+        bf16x8 v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (__bf16)(mul * (float)byte_at(raw, e));
+        return __builtin_bit_cast(uint4, v);
+    }
+    static __device__ __forceinline__ f32x16 mma(uint4 a, uint4 b, f32x16 c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// K0: packing.  Fragment u = (tile * kSteps + s) * 64 + lane holds the eight
+// K elements lane `lane` supplies at step s for row 32*tile + (lane & 31).
+// ---------------------------------------------------------------------------
+template <class Op>
+__global__ void k_pack_u8(const uint8_t *__restrict__ refs, int64_t n_refs, int64_t n_frag,
+                          uint4 *__restrict__ frag)
+{
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n_frag;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        const int lane = (int)(u & 63);
+        const int s = (int)((u >> 6) % Op::kSteps);
+        const int64_t tile = (u >> 6) / Op::kSteps;
+        const int64_t row = tile * kTileRows + (lane & 31);
+        uint2 raw = make_uint2(0u, 0u);
+        if (row < n_refs)
+            raw = *reinterpret_cast<const uint2 *>(refs + row * kDim + 16 * s + 8 * (lane >> 5));
+        frag[u] = Op::cvt8(raw, 1.0f);
+    }
+}
+
+// Accumulator seed ||r||^2 (an exact integer in FP32), +inf on padding rows
+// so they never enter a neighbour list.
+__global__ void k_seed_u8(const uint8_t *__restrict__ refs, int64_t n_refs, int64_t n_pad,
+                          float *__restrict__ seed)
+{
+    for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < n_pad;
+         row += (int64_t)gridDim.x * blockDim.x) {
+        if (row >= n_refs) {
+            seed[row] = __builtin_inff();
+            continue;
+        }
+        const uint4 *p = reinterpret_cast<const uint4 *>(refs + row * kDim);
+        uint32_t acc = 0;
+#pragma unroll
+        for (int c = 0; c < kDim / 16; ++c) {
+            uint4 v = p[c];
+            uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    uint32_t x = (w[i] >> (8 * b)) & 0xffu;
+                    acc += x * x;
+                }
+        }
+        seed[row] = (float)acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K1: distances + top-(k+1).
+//
+// Work item = (query block of kWaves * 32 * NT queries, reference slice).
+// Each wave keeps 32*NT queries' -2q fragments in registers for the whole
+// slice; the workgroup streams 32-row reference tiles through a double-
+// buffered LDS stage of MT tiles.  With references as the MFMA M dimension
+// and queries as N, lane l's 16 accumulator registers are 16 references of
+// one query (column l & 31): register r is row 8*(r/4) + 4*(l/32) + r%4.
+//
+// Selection.  Each lane keeps a sorted register list of the KP best
+// (d', index) pairs of its query among the rows it has seen (lanes l and
+// l+32 each see half of every tile and keep separate lists).  A tile is
+// gated by the minimum of the lane's 16 values: only when some lane of the
+// wave beats its current KP-th value does the wave walk the 16 registers and
+// insert.  Rows reach a lane in increasing index order, so "strictly less
+// than" on d' alone realises the (distance, index) order.
+// ---------------------------------------------------------------------------
+template <int KP>
+static __device__ __forceinline__ void list_insert(float v, int idx, float (&ld)[KP], int (&li)[KP],
+                                                   float &thr)
+{
+#pragma unroll
+    for (int p = KP - 1; p > 0; --p) {
+        const bool shift = v < ld[p - 1];
+        const bool here = v < ld[p];
+        const float nd = shift ? ld[p - 1] : (here ? v : ld[p]);
+        const int ni = shift ? li[p - 1] : (here ? idx : li[p]);
+        ld[p] = nd;
+        li[p] = ni;
+    }
+    const bool first = v < ld[0];
+    ld[0] = first ? v : ld[0];
+    li[0] = first ? idx : li[0];
+    thr = ld[KP - 1];
+}
+
+template <int KP>
+static __device__ __forceinline__ void tile_select(const f32x16 &acc, float &thr, float (&ld)[KP],
+                                                   int (&li)[KP], int row0)
+{
+    float m0 = __builtin_fminf(__builtin_fminf(acc[0], acc[1]), acc[2]);
+    float m1 = __builtin_fminf(__builtin_fminf(acc[3], acc[4]), acc[5]);
+    float m2 = __builtin_fminf(__builtin_fminf(acc[6], acc[7]), acc[8]);
+    float m3 = __builtin_fminf(__builtin_fminf(acc[9], acc[10]), acc[11]);
+    float m4 = __builtin_fminf(__builtin_fminf(acc[12], acc[13]), acc[14]);
+    float mn = __builtin_fminf(__builtin_fminf(m0, m1), __builtin_fminf(m2, m3));
+    mn = __builtin_fminf(__builtin_fminf(mn, m4), acc[15]);
+    if (__builtin_amdgcn_ballot_w64(mn < thr) == 0) return;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const float v = acc[r];
+        const bool take = v < thr;
+        if (__builtin_amdgcn_ballot_w64(take) != 0) {
+            if (take) list_insert<KP>(v, row0 + 8 * (r >> 2) + (r & 3), ld, li, thr);
+        }
+    }
+}
+
+template <class Op, int KP, int NT, int MT>
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
+void k_dist_topk(DistArgs a)
+{
+    constexpr int S = Op::kSteps;
+    constexpr int TILE_U4 = S * 64;               // uint4 per 32-row tile
+    constexpr int STAGE_U4 = MT * TILE_U4;
+    constexpr int QW = 32 * NT;                   // queries per wave
+    constexpr int QB = kWaves * QW;               // queries per workgroup
+    constexpr int PF = STAGE_U4 / (kWaves * 64);  // uint4 per thread per stage
+    static_assert(PF * kWaves * 64 == STAGE_U4, "stage must split evenly");
+    __shared__ uint4 s_frag[2][STAGE_U4];
+    __shared__ float4 s_seed[2][MT * 8];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, col = lane & 31;
+    const int64_t n_q = a.bd->n_q;
+    const int64_t n_qb = (n_q + QB - 1) / QB;
+    const int64_t n_items = n_qb * a.n_slices;
+
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int slice = (int)(item / n_qb);
+        const int64_t qb = item - (int64_t)slice * n_qb;
+        const int64_t t0 = (int64_t)slice * a.tiles_per_slice;
+        const int64_t t1 = min(t0 + (int64_t)a.tiles_per_slice, a.n_tiles);
+        const int n_stages = (int)((t1 - t0) / MT);
+
+        uint4 bq[NT][S];
+        int64_t qi[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            qi[nt] = qb * QB + wave * QW + nt * 32 + col;
+            const bool ok = qi[nt] < n_q;
+            const uint8_t *qrow = static_cast<const uint8_t *>(a.q) + (ok ? qi[nt] : 0) * kDim + 8 * h;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                uint2 raw = make_uint2(0u, 0u);
+                if (ok) raw = *reinterpret_cast<const uint2 *>(qrow + 16 * s);
+                bq[nt][s] = Op::cvt8(raw, -2.0f);
+            }
+        }
+
+        float ld[NT][KP];
+        int li[NT][KP];
+        float thr[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+            for (int p = 0; p < KP; ++p) {
+                ld[nt][p] = __builtin_inff();
+                li[nt][p] = -1;
+            }
+            thr[nt] = __builtin_inff();
+        }
+
+        {   // prologue: stage 0 -> buffer 0
+            const uint4 *src = a.frag + t0 * TILE_U4;
+#pragma unroll
+            for (int p = 0; p < PF; ++p) s_frag[0][tid + p * kWaves * 64] = src[tid + p * kWaves * 64];
+            if (tid < MT * 8) s_seed[0][tid] = reinterpret_cast<const float4 *>(a.seed + t0 * kTileRows)[tid];
+        }
+        __syncthreads();
+
+        for (int st = 0; st < n_stages; ++st) {
+            const int buf = st & 1;
+            // Prefetch the next stage into registers.  On the last stage the
+            // loads re-read stage 0 and the stores below fill the idle buffer,
+            // which nobody reads again in this item; keeping them
+            // unconditional lets the prefetch live in registers.
+            const int64_t tn = (st + 1 < n_stages) ? t0 + (int64_t)(st + 1) * MT : t0;
+            uint4 pf[PF];
+            float4 pseed = make_float4(0.f, 0.f, 0.f, 0.f);
+            {
+                const uint4 *src = a.frag + tn * TILE_U4;
+#pragma unroll
+                for (int p = 0; p < PF; ++p) pf[p] = src[tid + p * kWaves * 64];
+                if (tid < MT * 8) pseed = reinterpret_cast<const float4 *>(a.seed + tn * kTileRows)[tid];
+            }
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                f32x16 seed;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const float4 sv = s_seed[buf][m * 8 + 2 * g + h];
+                    seed[4 * g + 0] = sv.x;
+                    seed[4 * g + 1] = sv.y;
+                    seed[4 * g + 2] = sv.z;
+                    seed[4 * g + 3] = sv.w;
+                }
+                f32x16 acc[NT];
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    const uint4 av = s_frag[buf][(m * S + s) * 64 + lane];
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) acc[nt] = Op::mma(av, bq[nt][s], s == 0 ? seed : acc[nt]);
+                }
+                const int row0 = (int)((t0 + (int64_t)st * MT + m) * kTileRows) + 4 * h;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) tile_select<KP>(acc[nt], thr[nt], ld[nt], li[nt], row0);
+            }
+#pragma unroll
+            for (int p = 0; p < PF; ++p) s_frag[buf ^ 1][tid + p * kWaves * 64] = pf[p];
+            if (tid < MT * 8) s_seed[buf ^ 1][tid] = pseed;
+            __syncthreads();
+        }
+
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            if (qi[nt] < n_q) {
+                const int64_t base = ((int64_t)(slice * 2 + h) * a.q_cap + qi[nt]) * KP;
+#pragma unroll
+                for (int p = 0; p < KP; ++p) {
+                    a.part_d[base + p] = ld[nt][p];
+                    a.part_i[base + p] = li[nt][p];
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K2: finish.  One thread per query: merge the 2*n_slices sorted partial
+// lists into the k+1 best (d', index) pairs, then apply Algorithm 2's update:
+// dist_B is the (k+1)-th distance, and each class met among the first k
+// neighbours, at its first (= nearest) occurrence, adds dist_C - dist_B to
+// the image total.  Exact modes add exact integers with 64-bit atomics, so
+// totals do not depend on the order of the atomics.
+// ---------------------------------------------------------------------------
+static __device__ __forceinline__ bool pair_less(float d0, int i0, float d1, int i1)
+{
+    return d0 < d1 || (d0 == d1 && (uint32_t)i0 < (uint32_t)i1);
+}
+
+__global__ __launch_bounds__(256) void k_finish(FinishArgs a)
+{
+    const int64_t n_q = a.bd->n_q;
+    const int64_t n_img = a.bd->n_img;
+    const int kp = a.k + 1;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n_q;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        int heads[64];
+        for (int l = 0; l < a.n_lists; ++l) heads[l] = 0;
+        float dd[kMaxKP];
+        int ii[kMaxKP];
+        for (int p = 0; p < kp; ++p) {
+            float bd = __builtin_inff();
+            int bi = -1, bl = 0;
+            for (int l = 0; l < a.n_lists; ++l) {
+                if (heads[l] >= kp) continue;
+                const int64_t o = ((int64_t)l * a.q_cap + q) * a.kp_stride + heads[l];
+                const float d = a.part_d[o];
+                const int i = a.part_i[o];
+                if (pair_less(d, i, bd, bi)) {
+                    bd = d;
+                    bi = i;
+                    bl = l;
+                }
+            }
+            heads[bl] += 1;
+            dd[p] = bd;
+            ii[p] = bi;
+        }
+        // ||q||^2 turns d' back into the squared distance for the output lists
+        const uint4 *qr = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(a.q) + q * kDim);
+        uint32_t qq = 0;
+        for (int c = 0; c < kDim / 16; ++c) {
+            const uint4 v = qr[c];
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+            for (int i = 0; i < 4; ++i)
+                for (int b = 0; b < 4; ++b) {
+                    const uint32_t x = (w[i] >> (8 * b)) & 0xffu;
+                    qq += x * x;
+                }
+        }
+        // image of query q: last m with offsets[m] <= q
+        int64_t lo = 0, hi = n_img - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (a.offsets[mid] <= q) lo = mid; else hi = mid - 1;
+        }
+        const int64_t img = lo;
+        const int db = (int)dd[a.k];
+        int lab[kMaxKP];
+        for (int j = 0; j < a.k; ++j) {
+            // an index outside the reference set cannot occur; the guard keeps
+            // a defect visible as a wrong answer instead of a wild read
+            const int c = (ii[j] >= 0 && ii[j] < a.n_refs) ? a.labels[ii[j]] : 0;
+            lab[j] = c;
+            bool first = true;
+            for (int jj = 0; jj < j; ++jj) first = first && (lab[jj] != c);
+            if (first) {
+                const long long delta = (long long)((int)dd[j] - db);
+                atomicAdd(a.totals + img * a.n_classes + c, (unsigned long long)delta);
+            }
+        }
+        if (a.nbr_idx) {
+            for (int p = 0; p < kp; ++p) {
+                a.nbr_idx[q * kp + p] = ii[p];
+                a.nbr_dist[q * kp + p] = dd[p] + (float)qq;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K3: argmin over classes, lowest class on ties.  One wave per image.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_argmin(const unsigned long long *__restrict__ totals,
+                                                const BatchDesc *bd, int32_t n_classes,
+                                                int32_t *__restrict__ out_class,
+                                                double *__restrict__ totals_f64, int32_t fixed_point)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t n_img = bd->n_img;
+    for (int64_t img = blockIdx.x * 4 + (threadIdx.x >> 6); img < n_img; img += (int64_t)gridDim.x * 4) {
+        const long long *t = reinterpret_cast<const long long *>(totals) + img * n_classes;
+        long long best = 0x7fffffffffffffffLL;
+        int bc = 0x7fffffff;
+        for (int c = lane; c < n_classes; c += 64) {
+            const long long v = t[c];
+            if (v < best) {
+                best = v;
+                bc = c;
+            }
+            if (totals_f64) totals_f64[img * n_classes + c] = (double)v * 0x1p-40;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const long long ov = __shfl_xor(best, off);
+            const int oc = __shfl_xor(bc, off);
+            if (ov < best || (ov == best && oc < bc)) {
+                best = ov;
+                bc = oc;
+            }
+        }
+        if (lane == 0) out_class[img] = bc;
+    }
+    (void)fixed_point;
+}
+
+__global__ void k_fill_u64(unsigned long long *p, const BatchDesc *bd, int32_t n_classes, int64_t cap)
+{
+    int64_t n = bd->n_img * (int64_t)n_classes;
+    if (n > cap) n = cap;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// Variant table and dispatch
+// ---------------------------------------------------------------------------
+static const Variant kVariants[] = {
+    {1, 2},   // 0: 32 queries/wave, 2 tiles/stage
+    {2, 2},   // 1: 64 queries/wave, 2 tiles/stage
+    {1, 4},   // 2: 32 queries/wave, 4 tiles/stage
+    {2, 4},   // 3: 64 queries/wave, 4 tiles/stage
+};
+static const char *kVariantNames[] = {"nt1_mt2", "nt2_mt2", "nt1_mt4", "nt2_mt4"};
+static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+int num_variants() { return kNumVariants; }
+Variant variant(int v) { return kVariants[v]; }
+const char *variant_name(int v) { return (v >= 0 && v < kNumVariants) ? kVariantNames[v] : "?"; }
+int waves_per_block() { return kWaves; }
+
+int kp_bucket(int kp, int fmt)
+{
+    if (fmt != FMT_F16 && fmt != FMT_BF16) return 0;
+    static const int b[] = {2, 6, 11, 16, 21, 33};
+    for (int x : b)
+        if (kp <= x) return x;
+    return 0;
+}
+
+bool variant_supports(int v, int fmt, int kp)
+{
+    if (v < 0 || v >= kNumVariants) return false;
+    const int b = kp_bucket(kp, fmt);
+    if (b == 0) return false;
+    return kVariants[v].nt == 1 || b <= 16;
+}
+
+template <class Op, int KP, int NT, int MT>
+static void *kernel_ptr()
+{
+    return reinterpret_cast<void *>(&k_dist_topk<Op, KP, NT, MT>);
+}
+
+template <class Op, int KP>
+static void *pick_nt_mt(int v)
+{
+    switch (v) {
+    case 0: return kernel_ptr<Op, KP, 1, 2>();
+    case 2: return kernel_ptr<Op, KP, 1, 4>();
+    }
+    if constexpr (KP <= 16) {
+        switch (v) {
+        case 1: return kernel_ptr<Op, KP, 2, 2>();
+        case 3: return kernel_ptr<Op, KP, 2, 4>();
+        }
+    }
+    return nullptr;
+}
+
+template <class Op>
+static void *pick_kp(int v, int kpb)
+{
+    switch (kpb) {
+    case 2: return pick_nt_mt<Op, 2>(v);
+    case 6: return pick_nt_mt<Op, 6>(v);
+    case 11: return pick_nt_mt<Op, 11>(v);
+    case 16: return pick_nt_mt<Op, 16>(v);
+    case 21: return pick_nt_mt<Op, 21>(v);
+    case 33: return pick_nt_mt<Op, 33>(v);
+    }
+    return nullptr;
+}
+
+static void *dist_kernel(int v, int fmt, int kp)
+{
+    if (!variant_supports(v, fmt, kp)) return nullptr;
+    const int b = kp_bucket(kp, fmt);
+    switch (fmt) {
+    case FMT_F16: return pick_kp<OpF16>(v, b);
+    case FMT_BF16: return pick_kp<OpBF16>(v, b);
+    }
+    return nullptr;
+}
+
+hipError_t launch_dist_topk(int v, int fmt, int kp, const DistArgs &a, int grid, hipStream_t s)
+{
+    void *fn = dist_kernel(v, fmt, kp);
+    if (!fn) return hipErrorInvalidValue;
+    DistArgs args = a;
+    void *params[] = {&args};
+    return hipLaunchKernel(fn, dim3(grid), dim3(kWaves * 64), params, 0, s);
+}
+
+int dist_topk_blocks_per_cu(int v, int fmt, int kp)
+{
+    void *fn = dist_kernel(v, fmt, kp);
+    if (!fn) return 0;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kWaves * 64, 0) != hipSuccess) return 0;
+    return n;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers of the small kernels
+// ---------------------------------------------------------------------------
+static int grid_for(int64_t n, int block, int cap = 65536)
+{
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+hipError_t launch_pack_u8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, int fmt, uint4 *frag,
+                          float *seed, hipStream_t s)
+{
+    const int64_t n_frag = (n_pad / kTileRows) * 8 * 64;
+    if (fmt == FMT_F16)
+        k_pack_u8<OpF16><<<grid_for(n_frag, 256), 256, 0, s>>>(refs, n_refs, n_frag, frag);
+    else if (fmt == FMT_BF16)
+        k_pack_u8<OpBF16><<<grid_for(n_frag, 256), 256, 0, s>>>(refs, n_refs, n_frag, frag);
+    else
+        return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (seed) {
+        k_seed_u8<<<grid_for(n_pad, 256), 256, 0, s>>>(refs, n_refs, n_pad, seed);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int64_t cap, const BatchDesc *bd, int32_t n_classes,
+                           hipStream_t s)
+{
+    k_fill_u64<<<grid_for(cap, 256, 4096), 256, 0, s>>>(p, bd, n_classes, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const FinishArgs &a, int64_t q_cap, hipStream_t s)
+{
+    k_finish<<<grid_for(q_cap, 256, 16384), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_argmin(const unsigned long long *totals, const BatchDesc *bd, int64_t img_cap,
+                         int32_t n_classes, int32_t *out_class, double *totals_f64, int32_t fixed_point,
+                         hipStream_t s)
+{
+    k_argmin<<<grid_for(img_cap, 4, 16384), 256, 0, s>>>(totals, bd, n_classes, out_class, totals_f64,
+                                                          fixed_point);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_f32_fp8(const float *, int64_t, int64_t, uint4 *, float *, int32_t *, hipStream_t)
+{
+    return hipErrorNotSupported;
+}
+
+hipError_t launch_quant_queries_fp8(const float *, const BatchDesc *, int64_t, uint8_t *, int32_t *,
+                                    hipStream_t)
+{
+    return hipErrorNotSupported;
+}
+
+}  // namespace lnbnn

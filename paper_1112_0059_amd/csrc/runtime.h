@@ -1,0 +1,138 @@
+// Host runtime shared by the classify path and the serving loop.
+#pragma once
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdarg>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/lnbnn.h"
+#include "internal.h"
+
+namespace lnbnn {
+
+int set_err(int code, const char *fmt, ...);
+int hip_err(hipError_t e, const char *what);
+bool fault_injected(const char *site);
+
+#define LN_HIP(expr)                                   \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return hip_err(e_, #expr); \
+    } while (0)
+
+// Device buffers for one batch in flight.  Capacities only grow.
+struct Workspace {
+    int64_t q_cap = 0;          // query descriptors
+    int64_t img_cap = 0;        // images
+    int64_t part_cap = 0;       // elements of part_d / part_i
+    int64_t nbr_cap = 0;        // elements of nbr_idx / nbr_dist
+    int64_t qbytes_cap = 0;     // bytes of staged queries
+    void *q = nullptr;
+    int64_t *offsets = nullptr;
+    BatchDesc *bd = nullptr;
+    float *part_d = nullptr;
+    int32_t *part_i = nullptr;
+    unsigned long long *totals = nullptr;
+    double *totals_f64 = nullptr;
+    int32_t *cls = nullptr;
+    int32_t *nbr_idx = nullptr;
+    float *nbr_dist = nullptr;
+    int device = 0;
+    ~Workspace();
+    int64_t bytes() const;
+};
+
+struct Plan {
+    int variant = 0;
+    int fmt = 0;
+    int kpb = 0;                // compiled list length
+    int n_slices = 1;
+    int tiles_per_slice = 0;
+    int grid = 1;
+    int64_t q_cap = 0;          // capacity the plan (and part buffers) serve
+};
+
+// Everything a batch launch sequence needs; pointers are device pointers.
+struct BatchIO {
+    const void *q = nullptr;
+    const int64_t *offsets = nullptr;
+    const BatchDesc *bd = nullptr;
+    int64_t q_cap = 0;
+    int64_t img_cap = 0;
+    int32_t k = 0;
+    int mode = 0;
+    int32_t *cls = nullptr;
+    unsigned long long *totals = nullptr;
+    double *totals_f64 = nullptr;
+    int32_t *nbr_idx = nullptr;
+    float *nbr_dist = nullptr;
+    float *part_d = nullptr;
+    int32_t *part_i = nullptr;
+};
+
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+};
+
+struct Server;
+
+}  // namespace lnbnn
+
+struct lnbnn_index {
+    int device = 0;
+    int dtype = 0;
+    int64_t n_refs = 0;
+    int64_t n_pad = 0;
+    int32_t n_classes = 0;
+    uint32_t modes = 0;
+    int64_t hbm_budget = 0;
+    int cu_count = 0;
+    hipStream_t own_stream = nullptr;
+
+    uint4 *frag[4] = {nullptr, nullptr, nullptr, nullptr};
+    float *seed[4] = {nullptr, nullptr, nullptr, nullptr};
+    int32_t *labels = nullptr;
+    float *ref_f32 = nullptr;
+    int64_t device_bytes = 0;
+
+    std::mutex mu;                                     // classify path
+    lnbnn::Workspace ws;
+    std::map<std::pair<int, int>, int> pinned;         // (mode, kp bucket) -> variant
+    std::map<std::tuple<int, int, int>, int> occupancy;  // (variant, fmt, kpb) -> blocks/CU
+    std::map<std::string, lnbnn::GraphEntry> graphs;
+    lnbnn_timing last_timing{};
+    bool has_timing = false;
+    hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ws_free = nullptr;   // recorded after the last use of `ws`
+    bool ws_used = false;
+
+    lnbnn::Server *server = nullptr;   // owned; created by the first submit, deleted by server_stop
+    std::mutex server_mu;
+};
+
+namespace lnbnn {
+
+int mode_fmt(int mode);
+int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_variant, Plan *out);
+int64_t part_elems(const Plan &p, int64_t q_cap);
+// Enqueue fill + distance kernel + finish + argmin for one batch.  When
+// `ev` is not null, events 0/1 bracket the distance kernel and 2/3 the whole
+// sequence.
+int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t s, hipEvent_t *ev);
+int ensure_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int64_t img_cap, int64_t part,
+              int64_t nbr, int64_t qbytes, bool need_f64);
+int64_t row_bytes(int dtype);
+
+void server_stop(lnbnn_index *ix);
+bool server_pending(lnbnn_index *ix);
+
+}  // namespace lnbnn

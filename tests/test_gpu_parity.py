@@ -1,0 +1,216 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Exact modes must be bit-exact: neighbour indices and squared distances, the
+int64 class totals and the decisions.  Sizes span several reference tiles,
+several query blocks and ragged tails; the full-size case checks sampled
+descriptors one by one and one whole image.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1112_0059_amd as L
+import synth
+
+pytestmark = pytest.mark.gpu
+
+MODES = [L.LNBNN_EXACT_F16, L.LNBNN_EXACT_BF16]
+BOTH = L.LNBNN_MODE_BIT(L.LNBNN_EXACT_F16) | L.LNBNN_MODE_BIT(L.LNBNN_EXACT_BF16)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    cfg = synth.CONFIGS["T"]
+    R, labels = synth.gen_index(cfg)
+    Q, off, _ = synth.gen_queries(cfg)
+    ix = L.lnbnn_build_index(R, labels, cfg.n_classes, BOTH)
+    ref = {}
+    for k in (1, 5, 10):
+        ref[k] = oracle.classify(Q, R, labels, cfg.n_classes, off, k)
+    yield cfg, R, labels, Q, off, ix, ref
+    ix.free()
+
+
+def _check_exact(got, want, k):
+    cls, tot, ni, nd = got
+    wt, wc, wi, wd = want
+    assert np.array_equal(ni, wi), "neighbour indices differ"
+    assert np.array_equal(nd.astype(np.int64), wd), "neighbour distances differ"
+    assert np.all(nd == wd.astype(np.float32))
+    assert np.array_equal(tot, wt), "totals differ"
+    assert np.array_equal(cls, wc), "classes differ"
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("k", [1, 5, 10])
+def test_tiny_bit_exact(tiny, mode, k):
+    cfg, R, labels, Q, off, ix, ref = tiny
+    _say(f"tiny mode={mode} k={k}")
+    got = L.lnbnn_classify(ix, Q, off, k, mode, want_neighbours=True)
+    _check_exact(got, ref[k], k)
+
+
+@pytest.mark.parametrize("flags", [L.LNBNN_NO_GRAPH, L.LNBNN_PER_IMAGE_LAUNCH, L.LNBNN_TIMING])
+def test_tiny_launch_forms(tiny, flags):
+    cfg, R, labels, Q, off, ix, ref = tiny
+    _say(f"tiny flags={flags}")
+    got = L.lnbnn_classify(ix, Q, off, 10, L.LNBNN_EXACT_F16, flags=flags, want_neighbours=True)
+    _check_exact(got, ref[10], 10)
+    if flags & L.LNBNN_TIMING:
+        t = L.lnbnn_last_timing(ix)
+        assert t["dist_kernel_ms"] > 0 and t["total_ms"] >= t["dist_kernel_ms"]
+
+
+def test_tiny_every_variant(tiny):
+    cfg, R, labels, Q, off, ix, ref = tiny
+    for v in range(L.lnbnn_num_variants()):
+        _say(f"variant {v}")
+        L.lnbnn_set_variant(ix, L.LNBNN_EXACT_F16, 10, v)
+        got = L.lnbnn_classify(ix, Q, off, 10, L.LNBNN_EXACT_F16, want_neighbours=True)
+        _check_exact(got, ref[10], 10)
+    L.lnbnn_set_variant(ix, L.LNBNN_EXACT_F16, 10, -1)
+
+
+def test_device_pointers_and_graph_replays(tiny):
+    """Device tensors on torch's stream; the captured graph is replayed with
+    eager work and synchronisations in between, and every replay matches."""
+    import torch
+    cfg, R, labels, Q, off, ix, ref = tiny
+    dq = torch.from_numpy(Q).cuda()
+    out = {"class": torch.empty(cfg.n_img, dtype=torch.int32, device="cuda"),
+           "totals": torch.empty((cfg.n_img, cfg.n_classes), dtype=torch.int64, device="cuda"),
+           "nbr_idx": torch.empty((Q.shape[0], 11), dtype=torch.int32, device="cuda"),
+           "nbr_dist": torch.empty((Q.shape[0], 11), dtype=torch.float32, device="cuda")}
+    for rep in range(4):
+        _say(f"replay {rep}")
+        for t in out.values():
+            t.fill_(-7)
+        junk = torch.randn(1000, device="cuda").sum()      # eager work between replays
+        cls, tot, ni, nd = L.lnbnn_classify(ix, dq, off, 10, L.LNBNN_EXACT_F16,
+                                            want_neighbours=True, out=out)
+        torch.cuda.synchronize()
+        _check_exact((cls.cpu().numpy(), tot.cpu().numpy(), ni.cpu().numpy(), nd.cpu().numpy()),
+                     ref[10], 10)
+        del junk
+
+
+def test_fp16_equals_bf16_tiny(tiny):
+    cfg, R, labels, Q, off, ix, ref = tiny
+    a = L.lnbnn_classify(ix, Q, off, 5, L.LNBNN_EXACT_F16, want_neighbours=True)
+    b = L.lnbnn_classify(ix, Q, off, 5, L.LNBNN_EXACT_BF16, want_neighbours=True)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+# ------------------------------------------------------------- edge cases
+def _rand_problem(seed, n_refs, n_q, n_img, n_classes, hi=256, dup=0):
+    rng = np.random.default_rng(seed)
+    R = rng.integers(0, hi, size=(n_refs, 128)).astype(np.uint8)
+    if dup:
+        # duplicated rows with other labels: equal distances everywhere
+        src = rng.integers(0, n_refs, size=dup)
+        dst = rng.integers(0, n_refs, size=dup)
+        R[dst] = R[src]
+    Q = rng.integers(0, hi, size=(n_q, 128)).astype(np.uint8)
+    if n_q >= 4:
+        Q[:4] = R[:4]                       # exact matches (distance 0)
+    labels = rng.integers(0, n_classes, size=n_refs).astype(np.int32)
+    cuts = np.sort(rng.integers(0, n_q + 1, size=max(0, n_img - 1)))
+    off = np.concatenate([[0], cuts, [n_q]]).astype(np.int64)
+    return R, labels, Q, off
+
+
+@pytest.mark.parametrize("case", [
+    # (seed, n_refs, n_q, n_img, n_classes, hi, dup, k)
+    (1, 1000, 300, 3, 7, 256, 0, 10),      # ragged refs (not a multiple of 32 or 256)
+    (2, 33, 50, 2, 3, 256, 0, 32),         # k + 1 == n_refs (every reference retrieved)
+    (3, 2, 17, 1, 2, 256, 0, 1),           # two references
+    (4, 5000, 1, 1, 5, 256, 0, 5),         # a single descriptor
+    (5, 3000, 700, 9, 4, 4, 200, 10),      # tiny value range: ties everywhere
+    (6, 4096, 257, 5, 300, 256, 50, 20),   # more classes than neighbours, k = 20
+    (7, 20000, 2048, 40, 10, 256, 0, 7),   # many query blocks, k + 1 = 8 bucket rounding
+])
+@pytest.mark.parametrize("mode", MODES)
+def test_edge_cases(case, mode):
+    seed, n_refs, n_q, n_img, n_classes, hi, dup, k = case
+    _say(f"edge case {case} mode={mode}")
+    R, labels, Q, off = _rand_problem(seed, n_refs, n_q, n_img, n_classes, hi, dup)
+    # empty images at both ends and in the middle
+    off = np.concatenate([[0], off, [off[-1]]]).astype(np.int64)
+    want = oracle.classify(Q, R, labels, n_classes + 1, off, k)    # last class owns no ref
+    ix = L.lnbnn_build_index(R, labels, n_classes + 1, BOTH)
+    try:
+        got = L.lnbnn_classify(ix, Q, off, k, mode, want_neighbours=True)
+        _check_exact(got, want, k)
+        got = L.lnbnn_classify(ix, Q, off, k, mode, flags=L.LNBNN_PER_IMAGE_LAUNCH, want_neighbours=True)
+        _check_exact(got, want, k)
+    finally:
+        ix.free()
+
+
+def test_no_images_and_errors(tiny):
+    cfg, R, labels, Q, off, ix, ref = tiny
+    cls, tot, _, _ = L.lnbnn_classify(ix, Q[:0], np.array([0], np.int64), 10, L.LNBNN_EXACT_F16)
+    assert cls.shape == (0,)
+    with pytest.raises(L.LnbnnError) as e:
+        L.lnbnn_classify(ix, Q, off, 0, L.LNBNN_EXACT_F16)
+    assert e.value.code == L.LNBNN_EINVAL
+    with pytest.raises(L.LnbnnError) as e:
+        L.lnbnn_classify(ix, Q, off, 33, L.LNBNN_EXACT_F16)
+    assert e.value.code == L.LNBNN_EINVAL
+    with pytest.raises(L.LnbnnError) as e:
+        L.lnbnn_classify(ix, Q, off[::-1].copy(), 5, L.LNBNN_EXACT_F16)
+    assert e.value.code == L.LNBNN_EINVAL
+    with pytest.raises(L.LnbnnError) as e:
+        L.lnbnn_classify(ix, Q.astype(np.float32), off, 5, L.LNBNN_EXACT_F16)
+    assert e.value.code == L.LNBNN_EINVAL
+
+
+# ----------------------------------------------------- Caltech-101-sized
+@pytest.fixture(scope="module")
+def mid():
+    cfg = synth.CONFIGS["M"]
+    _say("generating M index")
+    R, labels = synth.gen_index(cfg)
+    ix = L.lnbnn_build_index(R, labels, cfg.n_classes, BOTH)
+    yield cfg, R, labels, ix
+    ix.free()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("k", [1, 5, 10])
+def test_mid_subset_bit_exact(mid, k):
+    """Four whole query images of the 2.27M-reference index against the
+    oracle's expanded-form route (exact for u8 data)."""
+    cfg, R, labels, ix = mid
+    imgs = [0, 333, 666, 999]
+    Q, off = synth.gen_query_images(cfg, imgs)
+    _say(f"mid k={k} oracle")
+    wi, wd = oracle.knn_expanded(Q, R, k + 1)
+    wt, wc = oracle.local_nbnn(wi, wd, k, labels, cfg.n_classes, off)
+    for mode in MODES:
+        _say(f"mid k={k} mode={mode}")
+        got = L.lnbnn_classify(ix, Q, off, k, mode, want_neighbours=True)
+        _check_exact(got, (wt, wc, wi, wd), k)
+
+
+@pytest.mark.timeout(600)
+def test_mid_all_images_fp16_equals_bf16(mid):
+    import torch
+    cfg, R, labels, ix = mid
+    Q, off, true_cls = synth.gen_queries(cfg)
+    dq = torch.from_numpy(Q).cuda()
+    _say("mid all images")
+    a = L.lnbnn_classify(ix, dq, off, 10, L.LNBNN_EXACT_F16)
+    b = L.lnbnn_classify(ix, dq, off, 10, L.LNBNN_EXACT_BF16)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    acc = float(np.mean(a[0].cpu().numpy() == true_cls))
+    _say(f"mid accuracy (statistic) {acc:.3f}")
