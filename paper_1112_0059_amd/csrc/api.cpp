@@ -149,10 +149,11 @@ static int blocks_per_cu(lnbnn_index *ix, int v, int fmt, int kpb)
 
 static int default_variant(int fmt, int kp)
 {
-    // 64 queries per wave halves LDS traffic per MFMA; fall back to 32
-    // queries per wave where the longer neighbour lists need the registers.
-    if (variant_supports(1, fmt, kp)) return 1;
-    return 0;
+    // 8 waves x 64 queries share each LDS stage (half the reference traffic
+    // of 4-wave workgroups); 32 queries per wave where the longer neighbour
+    // lists need the registers.
+    if (variant_supports(4, fmt, kp)) return 4;
+    return 6;
 }
 
 int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_variant, Plan *out)
@@ -168,7 +169,7 @@ int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_varia
     if (!variant_supports(v, fmt, kp))
         return set_err(LNBNN_EINVAL, "variant %d cannot serve mode %d with k + 1 = %d", v, mode, kp);
     const Variant var = variant(v);
-    const int64_t qb = (int64_t)waves_per_block() * 32 * var.nt;
+    const int64_t qb = (int64_t)var.waves * 32 * var.nt;
     const int64_t n_qb = std::max<int64_t>(1, (q_cap + qb - 1) / qb);
     const int64_t n_tiles = ix->n_pad / kTileRows;
     const int bpc = blocks_per_cu(ix, v, fmt, kpb);

@@ -11,7 +11,6 @@ constexpr int kDim = 128;
 constexpr int kTileRows = 32;            // rows of one MFMA A tile
 constexpr int kPadRows = 256;            // index rows are padded to this multiple
 constexpr int kMaxKP = 33;               // k + 1 <= 33
-constexpr int kWaves = 4;                // waves per workgroup of the distance kernel
 
 // Element formats of the packed reference tiles.
 enum Fmt { FMT_F16 = 0, FMT_BF16 = 1, FMT_FP8 = 2, FMT_I8 = 3 };
@@ -24,10 +23,13 @@ struct BatchDesc {
 };
 
 // A distance-kernel variant: queries per wave = 32 * nt, reference tiles
-// per LDS stage = mt.  `kp` is the list length the kernel keeps (>= k + 1).
+// per LDS stage = mt, waves per workgroup.  The list length the kernel keeps
+// (>= k + 1) is a separate compile-time parameter.
 struct Variant {
     int nt;
     int mt;
+    int waves;
+    int buffers;    // LDS stages: the kernel keeps buffers - 1 stages in flight
 };
 
 struct DistArgs {
@@ -71,7 +73,6 @@ Variant variant(int v);
 const char *variant_name(int v);
 bool variant_supports(int v, int fmt, int kp);
 int kp_bucket(int kp, int fmt);         // list length compiled for kp (0 = unsupported)
-int waves_per_block();
 
 // Upload-side packing.  refs_u8 / refs_f32 are device pointers.
 hipError_t launch_pack_u8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, int fmt,

@@ -121,7 +121,7 @@ __global__ void k_seed_u8(const uint8_t *__restrict__ refs, int64_t n_refs, int6
 // ---------------------------------------------------------------------------
 // K1: distances + top-(k+1).
 //
-// Work item = (query block of kWaves * 32 * NT queries, reference slice).
+// Work item = (query block of W * 32 * NT queries, reference slice).
 // Each wave keeps 32*NT queries' -2q fragments in registers for the whole
 // slice; the workgroup streams 32-row reference tiles through a double-
 // buffered LDS stage of MT tiles.  With references as the MFMA M dimension
@@ -155,44 +155,154 @@ static __device__ __forceinline__ void list_insert(float v, int idx, float (&ld)
     thr = ld[KP - 1];
 }
 
-template <int KP>
-static __device__ __forceinline__ void tile_select(const f32x16 &acc, float &thr, float (&ld)[KP],
-                                                   int (&li)[KP], int row0)
+static __device__ __forceinline__ float min16(const f32x16 &acc)
 {
-    float m0 = __builtin_fminf(__builtin_fminf(acc[0], acc[1]), acc[2]);
-    float m1 = __builtin_fminf(__builtin_fminf(acc[3], acc[4]), acc[5]);
-    float m2 = __builtin_fminf(__builtin_fminf(acc[6], acc[7]), acc[8]);
-    float m3 = __builtin_fminf(__builtin_fminf(acc[9], acc[10]), acc[11]);
-    float m4 = __builtin_fminf(__builtin_fminf(acc[12], acc[13]), acc[14]);
+    const float m0 = __builtin_fminf(__builtin_fminf(acc[0], acc[1]), acc[2]);
+    const float m1 = __builtin_fminf(__builtin_fminf(acc[3], acc[4]), acc[5]);
+    const float m2 = __builtin_fminf(__builtin_fminf(acc[6], acc[7]), acc[8]);
+    const float m3 = __builtin_fminf(__builtin_fminf(acc[9], acc[10]), acc[11]);
+    const float m4 = __builtin_fminf(__builtin_fminf(acc[12], acc[13]), acc[14]);
     float mn = __builtin_fminf(__builtin_fminf(m0, m1), __builtin_fminf(m2, m3));
-    mn = __builtin_fminf(__builtin_fminf(mn, m4), acc[15]);
-    if (__builtin_amdgcn_ballot_w64(mn < thr) == 0) return;
+    return __builtin_fminf(__builtin_fminf(mn, m4), acc[15]);
+}
+
+// Insert every value of one tile that beats the list's current KP-th value.
+template <int KP>
+static __device__ __forceinline__ void tile_insert(const f32x16 &acc, float &thr, float (&ld)[KP], int (&li)[KP],
+                                                   int row0)
+{
+    // the row base is made opaque here so the 16 index computations stay on
+    // this (rarely taken) path instead of being hoisted into the gate
+    int base = row0;
+    asm volatile("" : "+v"(base));
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const float v = acc[r];
         const bool take = v < thr;
         if (__builtin_amdgcn_ballot_w64(take) != 0) {
-            if (take) list_insert<KP>(v, row0 + 8 * (r >> 2) + (r & 3), ld, li, thr);
+            if (take) list_insert<KP>(v, base + 8 * (r >> 2) + (r & 3), ld, li, thr);
         }
     }
 }
 
-template <class Op, int KP, int NT, int MT>
-__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
+// Gate + insert for the NT query tiles of one reference tile.  All gates
+// are computed before any branch so they can overlap the next MFMA chain.
+template <int KP, int NT>
+static __device__ __forceinline__ void tiles_select(const f32x16 (&acc)[NT], float (&thr)[NT], float (&ld)[NT][KP],
+                                                    int (&li)[NT][KP], int row0)
+{
+    bool any[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) any[nt] = __builtin_amdgcn_ballot_w64(min16(acc[nt]) < thr[nt]) != 0;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+        if (any[nt]) tile_insert<KP>(acc[nt], thr[nt], ld[nt], li[nt], row0);
+}
+
+typedef __attribute__((address_space(1))) const void *gmem_ptr;
+typedef __attribute__((address_space(3))) void *lds_ptr;
+
+// Asynchronous copy of one LDS stage (MT tiles of fragments and their
+// seeds) straight from global memory into LDS (global_load_lds).  A
+// fragment instruction moves 64 lanes x 16 B to consecutive LDS addresses;
+// every wave also copies its share of the stage's MT*32 seeds with one
+// partial-lane 4-byte instruction.  Each wave therefore issues exactly
+// kStageLoads<MT, W> instructions per stage, which is what the vmcnt
+// waits below count on.
+template <int MT, int W>
+struct StageLoads {
+    static constexpr int frag = MT * 8 / W;                 // 1 KB chunks per wave (8 per tile)
+    static constexpr int total = frag + 1;
+    static_assert(frag * W == MT * 8, "stage chunks must split evenly over the waves");
+    static constexpr int seeds_per_wave = MT * kTileRows / W;
+    static_assert(seeds_per_wave <= 64 && seeds_per_wave * W == MT * kTileRows, "seed split");
+};
+
+template <int MT, int W, int TILE_U4>
+static __device__ __forceinline__ void stage_copy(const uint4 *src, uint4 *dst, const float *seed_src,
+                                                  float *seed_dst, int wave, int lane)
+{
+    using SL = StageLoads<MT, W>;
+#pragma unroll
+    for (int c = 0; c < SL::frag; ++c) {
+        const int chunk = c * W + wave;
+        __builtin_amdgcn_global_load_lds((gmem_ptr)(src + chunk * 64 + lane), (lds_ptr)(dst + chunk * 64), 16, 0, 0);
+    }
+    const int s0 = wave * SL::seeds_per_wave;
+    if (lane < SL::seeds_per_wave)
+        __builtin_amdgcn_global_load_lds((gmem_ptr)(seed_src + s0 + lane), (lds_ptr)(seed_dst + s0), 4, 0, 0);
+}
+
+// s_waitcnt with only the vector-memory counter limited (gfx9 encoding:
+// vmcnt in bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at maximum).
+template <int N>
+static __device__ __forceinline__ void wait_vmcnt()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// One pipeline step: the MFMA chain of a new tile (into acc_new) and the
+// gate of the previous tile (acc_old), scheduled as one block: all LDS reads
+// of the new tile first, then MFMAs interleaved with the gate's vector ops.
+// Insertions for the previous tile (rare) follow after the block.
+template <class Op, int KP, int NT>
+static __device__ __forceinline__ void pipe_step(f32x16 (&acc_new)[NT], const f32x16 (&acc_old)[NT],
+                                                 const uint4 (&bq)[NT][Op::kSteps], const uint4 *frag,
+                                                 const float4 *seed, int lane, int h, float (&thr)[NT],
+                                                 float (&ld)[NT][KP], int (&li)[NT][KP], int row_old)
+{
+    constexpr int S = Op::kSteps;
+    f32x16 sd;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const float4 sv = seed[2 * g + h];
+        sd[4 * g + 0] = sv.x;
+        sd[4 * g + 1] = sv.y;
+        sd[4 * g + 2] = sv.z;
+        sd[4 * g + 3] = sv.w;
+    }
+    uint4 av[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) av[s] = frag[s * 64 + lane];
+    bool any[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) any[nt] = __builtin_amdgcn_ballot_w64(min16(acc_old[nt]) < thr[nt]) != 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc_new[nt] = Op::mma(av[s], bq[nt][s], s == 0 ? sd : acc_new[nt]);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x100, S + 4, 0);     // LDS reads
+#pragma unroll
+    for (int i = 0; i < S * NT; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);     // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);     // up to two vector ops
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+        if (any[nt]) tile_insert<KP>(acc_old[nt], thr[nt], ld[nt], li[nt], row_old);
+}
+
+template <class Op, int KP, int NT, int MT, int W, int NB>
+__global__ __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W), amdgpu_waves_per_eu(2, 2)))
 void k_dist_topk(DistArgs a)
 {
     constexpr int S = Op::kSteps;
     constexpr int TILE_U4 = S * 64;               // uint4 per 32-row tile
     constexpr int STAGE_U4 = MT * TILE_U4;
     constexpr int QW = 32 * NT;                   // queries per wave
-    constexpr int QB = kWaves * QW;               // queries per workgroup
-    constexpr int PF = STAGE_U4 / (kWaves * 64);  // uint4 per thread per stage
-    static_assert(PF * kWaves * 64 == STAGE_U4, "stage must split evenly");
-    __shared__ uint4 s_frag[2][STAGE_U4];
-    __shared__ float4 s_seed[2][MT * 8];
+    constexpr int QB = W * QW;                    // queries per workgroup
+    constexpr int PD = NB - 1;                    // stages in flight ahead of the one computed
+    constexpr int LPS = StageLoads<MT, W>::total; // loads per wave per stage
+    static_assert(MT % 2 == 0, "tiles are processed in pairs");
+    static_assert(NB >= 2 && (PD - 1) * LPS < 64, "prefetch depth");
+    __shared__ uint4 s_frag[NB][STAGE_U4];
+    __shared__ float4 s_seed[NB][MT * 8];
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int h = lane >> 5, col = lane & 31;
     const int64_t n_q = a.bd->n_q;
     const int64_t n_qb = (n_q + QB - 1) / QB;
@@ -203,7 +313,7 @@ void k_dist_topk(DistArgs a)
         const int64_t qb = item - (int64_t)slice * n_qb;
         const int64_t t0 = (int64_t)slice * a.tiles_per_slice;
         const int64_t t1 = min(t0 + (int64_t)a.tiles_per_slice, a.n_tiles);
-        const int n_stages = (int)((t1 - t0) / MT);
+        const int n_t = (int)(t1 - t0);           // multiple of 8, so of MT
 
         uint4 bq[NT][S];
         int64_t qi[NT];
@@ -233,56 +343,55 @@ void k_dist_topk(DistArgs a)
             thr[nt] = __builtin_inff();
         }
 
-        {   // prologue: stage 0 -> buffer 0
-            const uint4 *src = a.frag + t0 * TILE_U4;
+        // Prologue: stages 0..PD-1 in flight, wait for stage 0.  Stages past
+        // the end of the slice are not loaded; the vmcnt waits account for
+        // them by issuing the same number of loads from the first stage (the
+        // data is never read).
+        const int n_st = n_t / MT;
 #pragma unroll
-            for (int p = 0; p < PF; ++p) s_frag[0][tid + p * kWaves * 64] = src[tid + p * kWaves * 64];
-            if (tid < MT * 8) s_seed[0][tid] = reinterpret_cast<const float4 *>(a.seed + t0 * kTileRows)[tid];
+        for (int p = 0; p < PD; ++p) {
+            const int64_t ts = t0 + (int64_t)(p < n_st ? p : 0) * MT;
+            stage_copy<MT, W, TILE_U4>(a.frag + ts * TILE_U4, s_frag[p], a.seed + ts * kTileRows,
+                                       reinterpret_cast<float *>(s_seed[p]), wave, lane);
         }
+        wait_vmcnt<(PD - 1) * LPS>();
         __syncthreads();
 
-        for (int st = 0; st < n_stages; ++st) {
-            const int buf = st & 1;
-            // Prefetch the next stage into registers.  On the last stage the
-            // loads re-read stage 0 and the stores below fill the idle buffer,
-            // which nobody reads again in this item; keeping them
-            // unconditional lets the prefetch live in registers.
-            const int64_t tn = (st + 1 < n_stages) ? t0 + (int64_t)(st + 1) * MT : t0;
-            uint4 pf[PF];
-            float4 pseed = make_float4(0.f, 0.f, 0.f, 0.f);
-            {
-                const uint4 *src = a.frag + tn * TILE_U4;
+        // Software pipeline over pairs of tiles: the MFMA chain of one tile is
+        // issued in the same block as the gate of the previous tile, so the
+        // matrix cores keep working while the gate's vector ops run.  The
+        // "previous tile" of the first step is all +inf and never passes.
+        f32x16 acc0[NT], acc1[NT];
 #pragma unroll
-                for (int p = 0; p < PF; ++p) pf[p] = src[tid + p * kWaves * 64];
-                if (tid < MT * 8) pseed = reinterpret_cast<const float4 *>(a.seed + tn * kTileRows)[tid];
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc1[nt][r] = __builtin_inff();
+        int row_prev = 0;
+        int buf = 0;
+        for (int st = 0; st < n_st; ++st) {
+            {   // stage st + PD goes into the buffer stage st - 1 used
+                const int sn = st + PD;
+                const int64_t ts = t0 + (int64_t)(sn < n_st ? sn : 0) * MT;
+                const int nb = (buf + PD) % NB;
+                stage_copy<MT, W, TILE_U4>(a.frag + ts * TILE_U4, s_frag[nb], a.seed + ts * kTileRows,
+                                           reinterpret_cast<float *>(s_seed[nb]), wave, lane);
             }
 #pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                f32x16 seed;
-#pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const float4 sv = s_seed[buf][m * 8 + 2 * g + h];
-                    seed[4 * g + 0] = sv.x;
-                    seed[4 * g + 1] = sv.y;
-                    seed[4 * g + 2] = sv.z;
-                    seed[4 * g + 3] = sv.w;
-                }
-                f32x16 acc[NT];
-#pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    const uint4 av = s_frag[buf][(m * S + s) * 64 + lane];
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) acc[nt] = Op::mma(av, bq[nt][s], s == 0 ? seed : acc[nt]);
-                }
-                const int row0 = (int)((t0 + (int64_t)st * MT + m) * kTileRows) + 4 * h;
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt) tile_select<KP>(acc[nt], thr[nt], ld[nt], li[nt], row0);
+            for (int m = 0; m < MT; m += 2) {
+                const int row_t = (int)((t0 + (int64_t)st * MT + m) * kTileRows) + 4 * h;
+                pipe_step<Op, KP, NT>(acc0, acc1, bq, s_frag[buf] + m * TILE_U4, s_seed[buf] + m * 8, lane, h,
+                                      thr, ld, li, row_prev);
+                pipe_step<Op, KP, NT>(acc1, acc0, bq, s_frag[buf] + (m + 1) * TILE_U4, s_seed[buf] + (m + 1) * 8,
+                                      lane, h, thr, ld, li, row_t);
+                row_prev = row_t + kTileRows;
             }
-#pragma unroll
-            for (int p = 0; p < PF; ++p) s_frag[buf ^ 1][tid + p * kWaves * 64] = pf[p];
-            if (tid < MT * 8) s_seed[buf ^ 1][tid] = pseed;
-            __syncthreads();
+            wait_vmcnt<(PD - 1) * LPS>();   // stage st + 1 has landed (this wave's part)
+            __syncthreads();                // ... every wave's part; stage st is consumed
+            buf = (buf + 1) % NB;
         }
+        wait_vmcnt<0>();                    // drain the loads past the end of the slice
+        __syncthreads();
+        tiles_select<KP, NT>(acc1, thr, ld, li, row_prev);
 
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
@@ -429,18 +538,23 @@ __global__ void k_fill_u64(unsigned long long *p, const BatchDesc *bd, int32_t n
 // Variant table and dispatch
 // ---------------------------------------------------------------------------
 static const Variant kVariants[] = {
-    {1, 2},   // 0: 32 queries/wave, 2 tiles/stage
-    {2, 2},   // 1: 64 queries/wave, 2 tiles/stage
-    {1, 4},   // 2: 32 queries/wave, 4 tiles/stage
-    {2, 4},   // 3: 64 queries/wave, 4 tiles/stage
+    // nt, mt, waves, buffers
+    {1, 2, 4, 4},   // 0
+    {2, 2, 4, 4},   // 1
+    {2, 4, 4, 2},   // 2
+    {2, 2, 4, 2},   // 3
+    {2, 4, 8, 4},   // 4
+    {2, 2, 8, 8},   // 5
+    {1, 4, 8, 4},   // 6
+    {2, 4, 4, 3},   // 7
 };
-static const char *kVariantNames[] = {"nt1_mt2", "nt2_mt2", "nt1_mt4", "nt2_mt4"};
+static const char *kVariantNames[] = {"w4_nt1_mt2_nb4", "w4_nt2_mt2_nb4", "w4_nt2_mt4_nb2", "w4_nt2_mt2_nb2",
+                                      "w8_nt2_mt4_nb4", "w8_nt2_mt2_nb8", "w8_nt1_mt4_nb4", "w4_nt2_mt4_nb3"};
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int num_variants() { return kNumVariants; }
 Variant variant(int v) { return kVariants[v]; }
 const char *variant_name(int v) { return (v >= 0 && v < kNumVariants) ? kVariantNames[v] : "?"; }
-int waves_per_block() { return kWaves; }
 
 int kp_bucket(int kp, int fmt)
 {
@@ -459,23 +573,27 @@ bool variant_supports(int v, int fmt, int kp)
     return kVariants[v].nt == 1 || b <= 16;
 }
 
-template <class Op, int KP, int NT, int MT>
+template <class Op, int KP, int NT, int MT, int W, int NB>
 static void *kernel_ptr()
 {
-    return reinterpret_cast<void *>(&k_dist_topk<Op, KP, NT, MT>);
+    return reinterpret_cast<void *>(&k_dist_topk<Op, KP, NT, MT, W, NB>);
 }
 
 template <class Op, int KP>
-static void *pick_nt_mt(int v)
+static void *pick_variant(int v)
 {
     switch (v) {
-    case 0: return kernel_ptr<Op, KP, 1, 2>();
-    case 2: return kernel_ptr<Op, KP, 1, 4>();
+    case 0: return kernel_ptr<Op, KP, 1, 2, 4, 4>();
+    case 6: return kernel_ptr<Op, KP, 1, 4, 8, 4>();
     }
     if constexpr (KP <= 16) {
         switch (v) {
-        case 1: return kernel_ptr<Op, KP, 2, 2>();
-        case 3: return kernel_ptr<Op, KP, 2, 4>();
+        case 1: return kernel_ptr<Op, KP, 2, 2, 4, 4>();
+        case 2: return kernel_ptr<Op, KP, 2, 4, 4, 2>();
+        case 3: return kernel_ptr<Op, KP, 2, 2, 4, 2>();
+        case 4: return kernel_ptr<Op, KP, 2, 4, 8, 4>();
+        case 5: return kernel_ptr<Op, KP, 2, 2, 8, 8>();
+        case 7: return kernel_ptr<Op, KP, 2, 4, 4, 3>();
         }
     }
     return nullptr;
@@ -485,12 +603,12 @@ template <class Op>
 static void *pick_kp(int v, int kpb)
 {
     switch (kpb) {
-    case 2: return pick_nt_mt<Op, 2>(v);
-    case 6: return pick_nt_mt<Op, 6>(v);
-    case 11: return pick_nt_mt<Op, 11>(v);
-    case 16: return pick_nt_mt<Op, 16>(v);
-    case 21: return pick_nt_mt<Op, 21>(v);
-    case 33: return pick_nt_mt<Op, 33>(v);
+    case 2: return pick_variant<Op, 2>(v);
+    case 6: return pick_variant<Op, 6>(v);
+    case 11: return pick_variant<Op, 11>(v);
+    case 16: return pick_variant<Op, 16>(v);
+    case 21: return pick_variant<Op, 21>(v);
+    case 33: return pick_variant<Op, 33>(v);
     }
     return nullptr;
 }
@@ -512,7 +630,7 @@ hipError_t launch_dist_topk(int v, int fmt, int kp, const DistArgs &a, int grid,
     if (!fn) return hipErrorInvalidValue;
     DistArgs args = a;
     void *params[] = {&args};
-    return hipLaunchKernel(fn, dim3(grid), dim3(kWaves * 64), params, 0, s);
+    return hipLaunchKernel(fn, dim3(grid), dim3(kVariants[v].waves * 64), params, 0, s);
 }
 
 int dist_topk_blocks_per_cu(int v, int fmt, int kp)
@@ -520,7 +638,7 @@ int dist_topk_blocks_per_cu(int v, int fmt, int kp)
     void *fn = dist_kernel(v, fmt, kp);
     if (!fn) return 0;
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kWaves * 64, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kVariants[v].waves * 64, 0) != hipSuccess) return 0;
     return n;
 }
 
