@@ -175,6 +175,18 @@ int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtype,
 /* Pin a kernel variant for (mode, k) on this index (-1 = heuristic choice). */
 int lnbnn_set_variant(lnbnn_index *ix, int mode, int32_t k, int32_t variant);
 
+/* Full launch tuning for (mode, k) on this index.  variant: kernel variant
+ * (-1 = heuristic); chunk_tiles: 32-row reference tiles a workgroup runs for
+ * one query block before moving to its next block (0 = default, else a
+ * multiple of 8); max_workgroups: cap on the persistent grid (0 = every
+ * resident slot).  No setting changes any result. */
+typedef struct lnbnn_tuning {
+    int32_t variant;
+    int32_t chunk_tiles;
+    int32_t max_workgroups;
+} lnbnn_tuning;
+int lnbnn_set_tuning(lnbnn_index *ix, int mode, int32_t k, const lnbnn_tuning *t);
+
 /* Number of kernel variants and a printable name of variant `v`. */
 int32_t lnbnn_num_variants(void);
 const char *lnbnn_variant_name(int32_t v);

@@ -45,6 +45,11 @@ class lnbnn_timing(ctypes.Structure):
                 ("tile_variant", ctypes.c_int32)]
 
 
+class lnbnn_tuning(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("chunk_tiles", ctypes.c_int32),
+                ("max_workgroups", ctypes.c_int32)]
+
+
 class lnbnn_req_stats(ctypes.Structure):
     _fields_ = [("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
                 ("t_start_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64),
@@ -62,6 +67,14 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    # One HIP runtime per process: torch ships its own libamdhip64 with the
+    # same SONAME as the system one the library links.  Loading torch first
+    # makes the dynamic loader bind the library to torch's copy; the other
+    # order would start a second runtime that torch can no longer use.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                              ctypes.c_uint32, ctypes.c_uint64)
@@ -76,6 +89,7 @@ def load():
         "lnbnn_autotune": ([P, P, ctypes.c_int, P, i32, i32, ctypes.c_int, ctypes.c_char_p, P, P],
                            ctypes.c_int),
         "lnbnn_set_variant": ([P, ctypes.c_int, i32, i32], ctypes.c_int),
+        "lnbnn_set_tuning": ([P, ctypes.c_int, i32, ctypes.POINTER(lnbnn_tuning)], ctypes.c_int),
         "lnbnn_num_variants": ([], i32),
         "lnbnn_variant_name": ([i32], ctypes.c_char_p),
         "lnbnn_submit": ([P, P, ctypes.c_int, i64, i32, ctypes.c_int, ctypes.POINTER(u64)],
@@ -252,6 +266,12 @@ def lnbnn_autotune(ix: Index, queries_dev, img_offsets, k: int, mode: int,
 
 def lnbnn_set_variant(ix: Index, mode: int, k: int, variant: int):
     _check(load().lnbnn_set_variant(ix.handle, int(mode), int(k), int(variant)))
+
+
+def lnbnn_set_tuning(ix: Index, mode: int, k: int, variant: int = -1, chunk_tiles: int = 0,
+                     max_workgroups: int = 0):
+    t = lnbnn_tuning(int(variant), int(chunk_tiles), int(max_workgroups))
+    _check(load().lnbnn_set_tuning(ix.handle, int(mode), int(k), ctypes.byref(t)))
 
 
 def lnbnn_num_variants() -> int:

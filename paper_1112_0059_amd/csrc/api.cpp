@@ -161,11 +161,11 @@ int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_varia
     const int fmt = mode_fmt(mode);
     const int kpb = kp_bucket(kp, fmt);
     if (kpb == 0) return set_err(LNBNN_EINVAL, "k + 1 = %d is not supported by mode %d", kp, mode);
-    int v = forced_variant;
-    if (v < 0) {
-        auto it = ix->pinned.find({mode, kpb});
-        v = it != ix->pinned.end() ? it->second : default_variant(fmt, kp);
-    }
+    lnbnn_tuning tu{-1, 0, 0};
+    auto it = ix->pinned.find({mode, kpb});
+    if (it != ix->pinned.end()) tu = it->second;
+    int v = forced_variant >= 0 ? forced_variant : tu.variant;
+    if (v < 0) v = default_variant(fmt, kp);
     if (!variant_supports(v, fmt, kp))
         return set_err(LNBNN_EINVAL, "variant %d cannot serve mode %d with k + 1 = %d", v, mode, kp);
     const Variant var = variant(v);
@@ -173,7 +173,8 @@ int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_varia
     const int64_t n_qb = std::max<int64_t>(1, (q_cap + qb - 1) / qb);
     const int64_t n_tiles = ix->n_pad / kTileRows;
     const int bpc = blocks_per_cu(ix, v, fmt, kpb);
-    const int64_t resident = (int64_t)ix->cu_count * bpc;
+    int64_t resident = (int64_t)ix->cu_count * bpc;
+    if (tu.max_workgroups > 0) resident = std::min<int64_t>(resident, tu.max_workgroups);
     // Split the reference set only when the query blocks alone cannot keep
     // every workgroup slot busy; each split costs one more partial list.
     int64_t want = 1;
@@ -187,6 +188,11 @@ int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_varia
     out->n_slices = (int)S;
     out->tiles_per_slice = (int)tps;
     out->grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_qb * S, resident));
+    // By default an item sweeps its whole slice with its lists in registers;
+    // a tuned chunk length makes workgroups that own several items walk the
+    // slice chunk by chunk instead (lists saved between chunks), which keeps
+    // the workgroups of an XCD on the same references at the same time.
+    out->chunk_tiles = tu.chunk_tiles > 0 ? (int)std::min<int64_t>(tu.chunk_tiles, tps) : (int)tps;
     out->q_cap = q_cap;
     return LNBNN_OK;
 }
@@ -206,6 +212,7 @@ int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t
     a.n_tiles = ix->n_pad / kTileRows;
     a.tiles_per_slice = p.tiles_per_slice;
     a.n_slices = p.n_slices;
+    a.chunk_tiles = p.chunk_tiles;
     a.q_cap = io.q_cap;
     a.part_d = io.part_d;
     a.part_i = io.part_i;
@@ -430,7 +437,7 @@ static int validate_classify(const lnbnn_index *ix, const void *queries, int dty
 static std::string graph_key(const Plan &p, const BatchIO &io)
 {
     std::ostringstream o;
-    o << p.variant << '/' << p.fmt << '/' << p.kpb << '/' << p.n_slices << '/' << p.tiles_per_slice << '/'
+    o << p.variant << '/' << p.fmt << '/' << p.kpb << '/' << p.n_slices << '/' << p.tiles_per_slice << '/' << p.chunk_tiles << '/'
       << p.grid << '/' << io.q_cap << '/' << io.img_cap << '/' << io.k << '/' << io.mode << '/' << io.q << '/'
       << io.offsets << '/' << io.bd << '/' << io.cls << '/' << io.totals << '/' << io.totals_f64 << '/'
       << io.nbr_idx << '/' << io.nbr_dist << '/' << io.part_d << '/' << io.part_i;
@@ -648,21 +655,29 @@ extern "C" int lnbnn_last_timing(const lnbnn_index *ix, lnbnn_timing *out)
 extern "C" int32_t lnbnn_num_variants(void) { return num_variants(); }
 extern "C" const char *lnbnn_variant_name(int32_t v) { return variant_name(v); }
 
-extern "C" int lnbnn_set_variant(lnbnn_index *ix, int mode, int32_t k, int32_t v)
+extern "C" int lnbnn_set_tuning(lnbnn_index *ix, int mode, int32_t k, const lnbnn_tuning *t)
 {
-    if (!ix) return set_err(LNBNN_EINVAL, "NULL index");
+    if (!ix || !t) return set_err(LNBNN_EINVAL, "NULL argument");
     if (mode < 0 || mode > 3 || !(ix->modes & LNBNN_MODE_BIT(mode))) return set_err(LNBNN_EINVAL, "bad mode");
     if (k < 1 || k > LNBNN_MAX_K) return set_err(LNBNN_EINVAL, "bad k");
+    if (t->chunk_tiles < 0 || t->chunk_tiles % 8 != 0) return set_err(LNBNN_EINVAL, "chunk_tiles must be a multiple of 8");
+    if (t->max_workgroups < 0) return set_err(LNBNN_EINVAL, "negative max_workgroups");
     const int fmt = mode_fmt(mode);
     const int kpb = kp_bucket(k + 1, fmt);
+    if (t->variant >= 0 && !variant_supports(t->variant, fmt, k + 1))
+        return set_err(LNBNN_EINVAL, "variant %d cannot serve k = %d", t->variant, k);
     std::lock_guard<std::mutex> lock(ix->mu);
-    if (v < 0) {
+    if (t->variant < 0 && t->chunk_tiles == 0 && t->max_workgroups == 0)
         ix->pinned.erase({mode, kpb});
-        return LNBNN_OK;
-    }
-    if (!variant_supports(v, fmt, k + 1)) return set_err(LNBNN_EINVAL, "variant %d cannot serve k = %d", v, k);
-    ix->pinned[{mode, kpb}] = v;
+    else
+        ix->pinned[{mode, kpb}] = *t;
     return LNBNN_OK;
+}
+
+extern "C" int lnbnn_set_variant(lnbnn_index *ix, int mode, int32_t k, int32_t v)
+{
+    lnbnn_tuning t{v < 0 ? -1 : v, 0, 0};
+    return lnbnn_set_tuning(ix, mode, k, &t);
 }
 
 // Flat JSON object of string -> integer, the tuning cache format.
@@ -723,7 +738,7 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
         auto it = m.find(key.str());
         if (it != m.end() && variant_supports(it->second, fmt, k + 1)) {
             std::lock_guard<std::mutex> lock(ix->mu);
-            ix->pinned[{mode, kpb}] = it->second;
+            ix->pinned[{mode, kpb}] = lnbnn_tuning{it->second, 0, 0};
             if (best_variant) *best_variant = it->second;
             return LNBNN_OK;
         }

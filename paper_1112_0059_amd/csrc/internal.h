@@ -42,6 +42,7 @@ struct DistArgs {
     int64_t n_tiles;            // 32-row tiles in the padded index (multiple of 8)
     int32_t tiles_per_slice;    // multiple of 8
     int32_t n_slices;
+    int32_t chunk_tiles;        // tiles one item runs before the workgroup moves on (multiple of 8)
     int64_t q_cap;              // capacity: part buffers are laid out for q_cap queries
     float *part_d;              // [n_slices * 2][q_cap][kp]
     int32_t *part_i;

@@ -307,100 +307,114 @@ void k_dist_topk(DistArgs a)
     const int64_t n_q = a.bd->n_q;
     const int64_t n_qb = (n_q + QB - 1) / QB;
     const int64_t n_items = n_qb * a.n_slices;
+    const int n_chunks = (a.tiles_per_slice + a.chunk_tiles - 1) / a.chunk_tiles;
 
-    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-        const int slice = (int)(item / n_qb);
-        const int64_t qb = item - (int64_t)slice * n_qb;
-        const int64_t t0 = (int64_t)slice * a.tiles_per_slice;
-        const int64_t t1 = min(t0 + (int64_t)a.tiles_per_slice, a.n_tiles);
-        const int n_t = (int)(t1 - t0);           // multiple of 8, so of MT
+    // Chunk-major walk: for every chunk of its slice, a workgroup runs all
+    // the (query block, slice) items it owns before moving to the next
+    // chunk, so the workgroups of an XCD stream the same few MB of
+    // references at about the same time and L2 serves them.  An item's
+    // neighbour lists live in registers while a chunk runs and in the
+    // partial-list buffer between chunks.
+    for (int c = 0; c < n_chunks; ++c) {
+        for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+            const int slice = (int)(item / n_qb);
+            const int64_t qb = item - (int64_t)slice * n_qb;
+            const int64_t ts0 = (int64_t)slice * a.tiles_per_slice;
+            const int64_t ts1 = min(ts0 + (int64_t)a.tiles_per_slice, a.n_tiles);
+            const int64_t t0 = ts0 + (int64_t)c * a.chunk_tiles;
+            if (t0 >= ts1) continue;                  // uniform: this slice has fewer chunks
+            const int64_t t1 = min(t0 + (int64_t)a.chunk_tiles, ts1);
+            const int n_t = (int)(t1 - t0);           // multiple of 8, so of MT
 
-        uint4 bq[NT][S];
-        int64_t qi[NT];
+            uint4 bq[NT][S];
+            int64_t qi[NT];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            qi[nt] = qb * QB + wave * QW + nt * 32 + col;
-            const bool ok = qi[nt] < n_q;
-            const uint8_t *qrow = static_cast<const uint8_t *>(a.q) + (ok ? qi[nt] : 0) * kDim + 8 * h;
+            for (int nt = 0; nt < NT; ++nt) {
+                qi[nt] = qb * QB + wave * QW + nt * 32 + col;
+                const bool ok = qi[nt] < n_q;
+                const uint8_t *qrow = static_cast<const uint8_t *>(a.q) + (ok ? qi[nt] : 0) * kDim + 8 * h;
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                uint2 raw = make_uint2(0u, 0u);
-                if (ok) raw = *reinterpret_cast<const uint2 *>(qrow + 16 * s);
-                bq[nt][s] = Op::cvt8(raw, -2.0f);
+                for (int s = 0; s < S; ++s) {
+                    uint2 raw = make_uint2(0u, 0u);
+                    if (ok) raw = *reinterpret_cast<const uint2 *>(qrow + 16 * s);
+                    bq[nt][s] = Op::cvt8(raw, -2.0f);
+                }
             }
-        }
 
-        float ld[NT][KP];
-        int li[NT][KP];
-        float thr[NT];
+            float ld[NT][KP];
+            int li[NT][KP];
+            float thr[NT];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-#pragma unroll
-            for (int p = 0; p < KP; ++p) {
-                ld[nt][p] = __builtin_inff();
-                li[nt][p] = -1;
-            }
-            thr[nt] = __builtin_inff();
-        }
-
-        // Prologue: stages 0..PD-1 in flight, wait for stage 0.  Stages past
-        // the end of the slice are not loaded; the vmcnt waits account for
-        // them by issuing the same number of loads from the first stage (the
-        // data is never read).
-        const int n_st = n_t / MT;
-#pragma unroll
-        for (int p = 0; p < PD; ++p) {
-            const int64_t ts = t0 + (int64_t)(p < n_st ? p : 0) * MT;
-            stage_copy<MT, W, TILE_U4>(a.frag + ts * TILE_U4, s_frag[p], a.seed + ts * kTileRows,
-                                       reinterpret_cast<float *>(s_seed[p]), wave, lane);
-        }
-        wait_vmcnt<(PD - 1) * LPS>();
-        __syncthreads();
-
-        // Software pipeline over pairs of tiles: the MFMA chain of one tile is
-        // issued in the same block as the gate of the previous tile, so the
-        // matrix cores keep working while the gate's vector ops run.  The
-        // "previous tile" of the first step is all +inf and never passes.
-        f32x16 acc0[NT], acc1[NT];
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc1[nt][r] = __builtin_inff();
-        int row_prev = 0;
-        int buf = 0;
-        for (int st = 0; st < n_st; ++st) {
-            {   // stage st + PD goes into the buffer stage st - 1 used
-                const int sn = st + PD;
-                const int64_t ts = t0 + (int64_t)(sn < n_st ? sn : 0) * MT;
-                const int nb = (buf + PD) % NB;
-                stage_copy<MT, W, TILE_U4>(a.frag + ts * TILE_U4, s_frag[nb], a.seed + ts * kTileRows,
-                                           reinterpret_cast<float *>(s_seed[nb]), wave, lane);
-            }
-#pragma unroll
-            for (int m = 0; m < MT; m += 2) {
-                const int row_t = (int)((t0 + (int64_t)st * MT + m) * kTileRows) + 4 * h;
-                pipe_step<Op, KP, NT>(acc0, acc1, bq, s_frag[buf] + m * TILE_U4, s_seed[buf] + m * 8, lane, h,
-                                      thr, ld, li, row_prev);
-                pipe_step<Op, KP, NT>(acc1, acc0, bq, s_frag[buf] + (m + 1) * TILE_U4, s_seed[buf] + (m + 1) * 8,
-                                      lane, h, thr, ld, li, row_t);
-                row_prev = row_t + kTileRows;
-            }
-            wait_vmcnt<(PD - 1) * LPS>();   // stage st + 1 has landed (this wave's part)
-            __syncthreads();                // ... every wave's part; stage st is consumed
-            buf = (buf + 1) % NB;
-        }
-        wait_vmcnt<0>();                    // drain the loads past the end of the slice
-        __syncthreads();
-        tiles_select<KP, NT>(acc1, thr, ld, li, row_prev);
-
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            if (qi[nt] < n_q) {
+            for (int nt = 0; nt < NT; ++nt) {
                 const int64_t base = ((int64_t)(slice * 2 + h) * a.q_cap + qi[nt]) * KP;
+                const bool load = c > 0 && qi[nt] < n_q;
 #pragma unroll
                 for (int p = 0; p < KP; ++p) {
-                    a.part_d[base + p] = ld[nt][p];
-                    a.part_i[base + p] = li[nt][p];
+                    ld[nt][p] = load ? a.part_d[base + p] : __builtin_inff();
+                    li[nt][p] = load ? a.part_i[base + p] : -1;
+                }
+                thr[nt] = ld[nt][KP - 1];
+            }
+
+            // Prologue: stages 0..PD-1 in flight, wait for stage 0.  Stages
+            // past the end of the chunk are not needed; to keep the vmcnt
+            // arithmetic uniform they re-load the chunk's first stage into a
+            // buffer that is never read.
+            const int n_st = n_t / MT;
+#pragma unroll
+            for (int p = 0; p < PD; ++p) {
+                const int64_t ts = t0 + (int64_t)(p < n_st ? p : 0) * MT;
+                stage_copy<MT, W, TILE_U4>(a.frag + ts * TILE_U4, s_frag[p], a.seed + ts * kTileRows,
+                                           reinterpret_cast<float *>(s_seed[p]), wave, lane);
+            }
+            wait_vmcnt<(PD - 1) * LPS>();
+            __syncthreads();
+
+            // Software pipeline over pairs of tiles: the MFMA chain of one
+            // tile is issued in the same block as the gate of the previous
+            // tile, so the matrix cores keep working while the gate's vector
+            // ops run.  The "previous tile" of the first step is all +inf.
+            f32x16 acc0[NT], acc1[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc1[nt][r] = __builtin_inff();
+            int row_prev = 0;
+            int buf = 0;
+            for (int st = 0; st < n_st; ++st) {
+                {   // stage st + PD goes into the buffer stage st - 1 used
+                    const int sn = st + PD;
+                    const int64_t ts = t0 + (int64_t)(sn < n_st ? sn : 0) * MT;
+                    const int nb = (buf + PD) % NB;
+                    stage_copy<MT, W, TILE_U4>(a.frag + ts * TILE_U4, s_frag[nb], a.seed + ts * kTileRows,
+                                               reinterpret_cast<float *>(s_seed[nb]), wave, lane);
+                }
+#pragma unroll
+                for (int m = 0; m < MT; m += 2) {
+                    const int row_t = (int)((t0 + (int64_t)st * MT + m) * kTileRows) + 4 * h;
+                    pipe_step<Op, KP, NT>(acc0, acc1, bq, s_frag[buf] + m * TILE_U4, s_seed[buf] + m * 8, lane, h,
+                                          thr, ld, li, row_prev);
+                    pipe_step<Op, KP, NT>(acc1, acc0, bq, s_frag[buf] + (m + 1) * TILE_U4,
+                                          s_seed[buf] + (m + 1) * 8, lane, h, thr, ld, li, row_t);
+                    row_prev = row_t + kTileRows;
+                }
+                wait_vmcnt<(PD - 1) * LPS>();   // stage st + 1 has landed (this wave's part)
+                __syncthreads();                // ... every wave's part; stage st is consumed
+                buf = (buf + 1) % NB;
+            }
+            wait_vmcnt<0>();                    // drain the loads past the end of the chunk
+            __syncthreads();
+            tiles_select<KP, NT>(acc1, thr, ld, li, row_prev);
+
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                if (qi[nt] < n_q) {
+                    const int64_t base = ((int64_t)(slice * 2 + h) * a.q_cap + qi[nt]) * KP;
+#pragma unroll
+                    for (int p = 0; p < KP; ++p) {
+                        a.part_d[base + p] = ld[nt][p];
+                        a.part_i[base + p] = li[nt][p];
+                    }
                 }
             }
         }

@@ -58,6 +58,7 @@ struct Plan {
     int n_slices = 1;
     int tiles_per_slice = 0;
     int grid = 1;
+    int chunk_tiles = 8;        // tiles per chunk of the chunk-major walk
     int64_t q_cap = 0;          // capacity the plan (and part buffers) serve
 };
 
@@ -106,7 +107,7 @@ struct lnbnn_index {
 
     std::mutex mu;                                     // classify path
     lnbnn::Workspace ws;
-    std::map<std::pair<int, int>, int> pinned;         // (mode, kp bucket) -> variant
+    std::map<std::pair<int, int>, lnbnn_tuning> pinned;   // (mode, kp bucket) -> launch tuning
     std::map<std::tuple<int, int, int>, int> occupancy;  // (variant, fmt, kpb) -> blocks/CU
     std::map<std::string, lnbnn::GraphEntry> graphs;
     lnbnn_timing last_timing{};

@@ -78,6 +78,20 @@ def test_tiny_every_variant(tiny):
     L.lnbnn_set_variant(ix, L.LNBNN_EXACT_F16, 10, -1)
 
 
+@pytest.mark.parametrize("variant", [0, 4, 6])
+def test_tiny_chunked_walk(tiny, variant):
+    """Few resident workgroups and short chunks: every workgroup owns several
+    query blocks and saves/restores their lists between chunks."""
+    cfg, R, labels, Q, off, ix, ref = tiny
+    _say(f"chunked walk variant {variant}")
+    L.lnbnn_set_tuning(ix, L.LNBNN_EXACT_F16, 10, variant=variant, chunk_tiles=8, max_workgroups=3)
+    try:
+        got = L.lnbnn_classify(ix, Q, off, 10, L.LNBNN_EXACT_F16, want_neighbours=True)
+        _check_exact(got, ref[10], 10)
+    finally:
+        L.lnbnn_set_tuning(ix, L.LNBNN_EXACT_F16, 10)
+
+
 def test_device_pointers_and_graph_replays(tiny):
     """Device tensors on torch's stream; the captured graph is replayed with
     eager work and synchronisations in between, and every replay matches."""
@@ -119,8 +133,8 @@ def _rand_problem(seed, n_refs, n_q, n_img, n_classes, hi=256, dup=0):
         dst = rng.integers(0, n_refs, size=dup)
         R[dst] = R[src]
     Q = rng.integers(0, hi, size=(n_q, 128)).astype(np.uint8)
-    if n_q >= 4:
-        Q[:4] = R[:4]                       # exact matches (distance 0)
+    m = min(4, n_q, n_refs)
+    Q[:m] = R[:m]                           # exact matches (distance 0)
     labels = rng.integers(0, n_classes, size=n_refs).astype(np.int32)
     cuts = np.sort(rng.integers(0, n_q + 1, size=max(0, n_img - 1)))
     off = np.concatenate([[0], cuts, [n_q]]).astype(np.int64)
