@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblnbnn.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "api.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "rerank.hip", "api.cpp", "serve.cpp"]
 ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

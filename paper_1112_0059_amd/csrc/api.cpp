@@ -65,7 +65,8 @@ int mode_fmt(int mode)
 
 Workspace::~Workspace()
 {
-    void *ps[] = {q, offsets, bd, part_d, part_i, totals, totals_f64, cls, nbr_idx, nbr_dist};
+    void *ps[] = {q, offsets, bd, part_d, part_i, totals, totals_f64, cls, nbr_idx, nbr_dist,
+                  q8, qsc, cand, upd_cls, upd_delta};
     for (void *p : ps)
         if (p) (void)hipFree(p);
 }
@@ -73,8 +74,11 @@ Workspace::~Workspace()
 int64_t Workspace::bytes() const
 {
     return qbytes_cap + (2 * img_cap + 2) * 8 + img_cap * (int64_t)sizeof(BatchDesc) + part_cap * 8 +
-           nbr_cap * 8 + img_cap * 4;
+           nbr_cap * 8 + img_cap * 4 + q8_cap * (kDim + 4) + cand_cap * 4 + upd_cap * 12;
 }
+
+// FP8 mode keeps 4k candidates per query (at least k + 1).
+int fp8_candidates(int k) { return 4 * k; }
 
 static int grow(void **p, int64_t have, int64_t need, size_t elem)
 {
@@ -136,6 +140,30 @@ int ensure_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int64_t img_cap, in
     return LNBNN_OK;
 }
 
+int ensure_fp8_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int n_cand, int k)
+{
+    const int64_t cand = q_cap * n_cand, upd = q_cap * k;
+    if (q_cap <= ws.q8_cap && cand <= ws.cand_cap && upd <= ws.upd_cap && ws.q8) return LNBNN_OK;
+    LN_HIP(hipDeviceSynchronize());
+    if (&ws == &ix->ws) drop_graphs(ix);
+    int rc;
+    if (q_cap > ws.q8_cap || !ws.q8) {
+        if ((rc = grow((void **)&ws.q8, 0, q_cap * (kDim / 16), 16))) return rc;
+        if ((rc = grow((void **)&ws.qsc, 0, q_cap, 4))) return rc;
+        ws.q8_cap = q_cap;
+    }
+    if (cand > ws.cand_cap || !ws.cand) {
+        if ((rc = grow((void **)&ws.cand, 0, cand, 4))) return rc;
+        ws.cand_cap = cand;
+    }
+    if (upd > ws.upd_cap || !ws.upd_cls) {
+        if ((rc = grow((void **)&ws.upd_cls, 0, upd, 4))) return rc;
+        if ((rc = grow((void **)&ws.upd_delta, 0, upd, 8))) return rc;
+        ws.upd_cap = upd;
+    }
+    return LNBNN_OK;
+}
+
 static int blocks_per_cu(lnbnn_index *ix, int v, int fmt, int kpb)
 {
     auto key = std::make_tuple(v, fmt, kpb);
@@ -149,6 +177,7 @@ static int blocks_per_cu(lnbnn_index *ix, int v, int fmt, int kpb)
 
 static int default_variant(int fmt, int kp)
 {
+    if (fmt == FMT_FP8) return variant_supports(4, fmt, kp) ? 4 : 6;
     // 8 waves x 64 queries share each LDS stage (half the reference traffic
     // of 4-wave workgroups); 32 queries per wave where the longer neighbour
     // lists need the registers.
@@ -202,13 +231,21 @@ int64_t part_elems(const Plan &p, int64_t q_cap) { return (int64_t)p.n_slices * 
 int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t s, hipEvent_t *ev)
 {
     if (fault_injected("launch")) return set_err(LNBNN_EDEVICE, "injected launch failure");
+    const bool fp8 = p.fmt == FMT_FP8;
     if (ev) LN_HIP(hipEventRecord(ev[2], s));
-    LN_HIP(launch_fill_u64(io.totals, io.img_cap * ix->n_classes, io.bd, ix->n_classes, s));
+    if (fp8)
+        LN_HIP(launch_fp8_qprep(static_cast<const float *>(io.q), io.bd, io.q_cap, io.q8, io.qsc, s));
+    else
+        LN_HIP(launch_fill_u64(io.totals, io.img_cap * ix->n_classes, io.bd, ix->n_classes, s));
     DistArgs a{};
-    a.q = io.q;
+    a.q = fp8 ? static_cast<const void *>(io.q8) : io.q;
+    a.q_scale = io.qsc;
     a.bd = io.bd;
     a.frag = ix->frag[p.fmt];
     a.seed = ix->seed[p.fmt];
+    // never read by the unscaled formats; any valid address keeps the
+    // kernel's pointer arithmetic defined
+    a.row_scale = ix->row_scale ? ix->row_scale : reinterpret_cast<const int32_t *>(a.seed);
     a.n_tiles = ix->n_pad / kTileRows;
     a.tiles_per_slice = p.tiles_per_slice;
     a.n_slices = p.n_slices;
@@ -219,26 +256,50 @@ int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t
     if (ev) LN_HIP(hipEventRecord(ev[0], s));
     LN_HIP(launch_dist_topk(p.variant, p.fmt, p.kpb, a, p.grid, s));
     if (ev) LN_HIP(hipEventRecord(ev[1], s));
-    FinishArgs f{};
-    f.q = io.q;
-    f.bd = io.bd;
-    f.offsets = io.offsets;
-    f.labels = ix->labels;
-    f.n_refs = ix->n_refs;
-    f.n_lists = 2 * p.n_slices;
-    f.kp_stride = p.kpb;
-    f.k = io.k;
-    f.n_classes = ix->n_classes;
-    f.q_cap = io.q_cap;
-    f.part_d = io.part_d;
-    f.part_i = io.part_i;
-    f.totals = io.totals;
-    f.nbr_idx = io.nbr_idx;
-    f.nbr_dist = io.nbr_dist;
-    f.fixed_point = p.fmt == FMT_FP8;
-    LN_HIP(launch_finish(f, io.q_cap, s));
-    LN_HIP(launch_argmin(io.totals, io.bd, io.img_cap, ix->n_classes, io.cls, io.totals_f64,
-                         p.fmt == FMT_FP8, s));
+    if (fp8) {
+        RerankArgs r{};
+        r.bd = io.bd;
+        r.offsets = io.offsets;
+        r.qf32 = static_cast<const float *>(io.q);
+        r.ref_f32 = ix->ref_f32;
+        r.labels = ix->labels;
+        r.n_refs = ix->n_refs;
+        r.n_lists = 2 * p.n_slices;
+        r.kp_stride = p.kpb;
+        r.n_cand = fp8_candidates(io.k);
+        r.k = io.k;
+        r.n_classes = ix->n_classes;
+        r.q_cap = io.q_cap;
+        r.part_d = io.part_d;
+        r.part_i = io.part_i;
+        r.cand = io.cand;
+        r.upd_cls = io.upd_cls;
+        r.upd_delta = io.upd_delta;
+        r.totals_f64 = io.totals_f64;
+        r.cls = io.cls;
+        r.nbr_idx = io.nbr_idx;
+        r.nbr_dist = io.nbr_dist;
+        LN_HIP(launch_rerank(r, io.q_cap, io.img_cap, s));
+    } else {
+        FinishArgs f{};
+        f.q = io.q;
+        f.bd = io.bd;
+        f.offsets = io.offsets;
+        f.labels = ix->labels;
+        f.n_refs = ix->n_refs;
+        f.n_lists = 2 * p.n_slices;
+        f.kp_stride = p.kpb;
+        f.k = io.k;
+        f.n_classes = ix->n_classes;
+        f.q_cap = io.q_cap;
+        f.part_d = io.part_d;
+        f.part_i = io.part_i;
+        f.totals = io.totals;
+        f.nbr_idx = io.nbr_idx;
+        f.nbr_dist = io.nbr_dist;
+        LN_HIP(launch_finish(f, io.q_cap, s));
+        LN_HIP(launch_argmin(io.totals, io.bd, io.img_cap, ix->n_classes, io.cls, s));
+    }
     if (ev) LN_HIP(hipEventRecord(ev[3], s));
     return LNBNN_OK;
 }
@@ -257,11 +318,14 @@ static int free_index_buffers(lnbnn_index *ix)
     // seeds of the two exact 16-bit formats share one buffer
     if (ix->seed[FMT_F16]) (void)hipFree(ix->seed[FMT_F16]);
     else if (ix->seed[FMT_BF16]) (void)hipFree(ix->seed[FMT_BF16]);
+    if (ix->seed[FMT_FP8]) (void)hipFree(ix->seed[FMT_FP8]);
     for (int f = 0; f < 4; ++f) ix->seed[f] = nullptr;
     if (ix->labels) (void)hipFree(ix->labels);
     if (ix->ref_f32) (void)hipFree(ix->ref_f32);
+    if (ix->row_scale) (void)hipFree(ix->row_scale);
     ix->labels = nullptr;
     ix->ref_f32 = nullptr;
+    ix->row_scale = nullptr;
     return LNBNN_OK;
 }
 
@@ -282,8 +346,8 @@ extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, in
     if (dtype == LNBNN_U8 && (mode_mask & ~exact))
         return set_err(LNBNN_EINVAL, "mode mask 0x%x: u8 data builds only the exact FP16/BF16 modes",
                        mode_mask);
-    if (dtype == LNBNN_F32)
-        return set_err(LNBNN_EINVAL, "float references (FP8 re-rank mode) are not built in this library");
+    if (dtype == LNBNN_F32 && mode_mask != LNBNN_MODE_BIT(LNBNN_FP8_RERANK))
+        return set_err(LNBNN_EINVAL, "mode mask 0x%x: float data builds only the FP8 re-rank mode", mode_mask);
     if (flags & ~(uint32_t)LNBNN_DEVICE_PTRS) return set_err(LNBNN_EINVAL, "unknown flags 0x%x", flags);
     const bool dev_in = flags & LNBNN_DEVICE_PTRS;
     if (!dev_in) {
@@ -334,29 +398,50 @@ extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, in
         if (e != hipSuccess) return fail(hip_err(e, "hipMemcpyAsync(labels)"));
     }
 
-    // references: stage u8 rows on the device, then pack per mode
-    const uint8_t *d_refs = static_cast<const uint8_t *>(refs);
+    // references: stage the rows on the device, then pack per mode
+    const int64_t rbytes = n_refs * row_bytes(dtype);
+    const void *d_refs = refs;
     void *staged = nullptr;
-    if (!dev_in) {
-        if ((rc = grow(&staged, 0, n_refs * kDim, 1))) return fail(rc);
-        hipError_t e = hipMemcpyAsync(staged, refs, (size_t)n_refs * kDim, hipMemcpyHostToDevice, s);
+    if (dtype == LNBNN_F32) {
+        // the FP32 rows stay resident for the exact re-rank
+        if ((rc = grow((void **)&ix->ref_f32, 0, n_refs * kDim, 4))) return fail(rc);
+        hipError_t e = hipMemcpyAsync(ix->ref_f32, refs, (size_t)rbytes,
+                                      dev_in ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return fail(hip_err(e, "hipMemcpyAsync(refs)"));
+        d_refs = ix->ref_f32;
+    } else if (!dev_in) {
+        if ((rc = grow(&staged, 0, rbytes, 1))) return fail(rc);
+        hipError_t e = hipMemcpyAsync(staged, refs, (size_t)rbytes, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) {
             (void)hipFree(staged);
             return fail(hip_err(e, "hipMemcpyAsync(refs)"));
         }
-        d_refs = static_cast<const uint8_t *>(staged);
+        d_refs = staged;
     }
     float *seed = nullptr;
-    int64_t bytes = n_refs * 4;
+    int64_t bytes = n_refs * 4 + (dtype == LNBNN_F32 ? rbytes : 0);
     rc = grow((void **)&seed, 0, ix->n_pad, 4);
     if (!rc) bytes += ix->n_pad * 4;
     bool seeded = false;
+    if (dtype == LNBNN_F32) {
+        if (!rc) rc = grow((void **)&ix->row_scale, 0, ix->n_pad, 4);
+        if (!rc) rc = grow((void **)&ix->frag[FMT_FP8], 0, ix->n_pad * kDim, 1);
+        if (!rc) {
+            bytes += ix->n_pad * (4 + kDim);
+            hipError_t e = launch_fp8_index(static_cast<const float *>(d_refs), n_refs, ix->n_pad,
+                                            ix->frag[FMT_FP8], seed, ix->row_scale, s);
+            if (e != hipSuccess) rc = hip_err(e, "fp8 pack");
+            seeded = true;
+            ix->seed[FMT_FP8] = seed;
+        }
+    }
     for (int mode : {LNBNN_EXACT_F16, LNBNN_EXACT_BF16}) {
-        if (rc || !(mode_mask & LNBNN_MODE_BIT(mode))) continue;
+        if (rc || dtype != LNBNN_U8 || !(mode_mask & LNBNN_MODE_BIT(mode))) continue;
         const int fmt = mode_fmt(mode);
         if ((rc = grow((void **)&ix->frag[fmt], 0, ix->n_pad * kDim * 2, 1))) break;
         bytes += ix->n_pad * kDim * 2;
-        hipError_t e = launch_pack_u8(d_refs, n_refs, ix->n_pad, fmt, ix->frag[fmt], seeded ? nullptr : seed, s);
+        hipError_t e = launch_pack_u8(static_cast<const uint8_t *>(d_refs), n_refs, ix->n_pad, fmt, ix->frag[fmt],
+                                      seeded ? nullptr : seed, s);
         if (e != hipSuccess) {
             rc = hip_err(e, "pack");
             break;
@@ -425,6 +510,10 @@ static int validate_classify(const lnbnn_index *ix, const void *queries, int dty
     if (dtype != want) return set_err(LNBNN_EINVAL, "dtype %d does not match mode %d", dtype, mode);
     if (k < 1 || k > LNBNN_MAX_K) return set_err(LNBNN_EINVAL, "k = %d outside [1, %d]", k, LNBNN_MAX_K);
     if ((int64_t)k + 1 > ix->n_refs) return set_err(LNBNN_EINVAL, "k + 1 > n_refs");
+    if (mode == LNBNN_FP8_RERANK) {
+        if (k > kMaxFp8K) return set_err(LNBNN_EINVAL, "FP8 re-rank mode needs k <= %d", kMaxFp8K);
+        if ((int64_t)fp8_candidates(k) > ix->n_refs) return set_err(LNBNN_EINVAL, "4k > n_refs");
+    }
     if ((nbr_idx == nullptr) != (nbr_dist == nullptr))
         return set_err(LNBNN_EINVAL, "out_nbr_idx and out_nbr_dist must both be set or both NULL");
     if (off[0] != 0) return set_err(LNBNN_EINVAL, "img_offsets[0] must be 0");
@@ -475,9 +564,10 @@ static int classify_per_image(lnbnn_index *ix, const void *dq, const int64_t *of
 {
     Workspace &ws = ix->ws;
     const int kp = k + 1;
+    const int list_len = mode == LNBNN_FP8_RERANK ? fp8_candidates(k) : kp;
     std::vector<Plan> plans(n_images);
     for (int32_t m = 0; m < n_images; ++m) {
-        int rc = make_plan(ix, mode, kp, std::max<int64_t>(1, off[m + 1] - off[m]), -1, &plans[m]);
+        int rc = make_plan(ix, mode, list_len, std::max<int64_t>(1, off[m + 1] - off[m]), -1, &plans[m]);
         if (rc) return rc;
     }
     std::vector<BatchDesc> bds(n_images);
@@ -507,6 +597,12 @@ static int classify_per_image(lnbnn_index *ix, const void *dq, const int64_t *of
         io.nbr_dist = nbr_dist ? nbr_dist + off[m] * kp : nullptr;
         io.part_d = ws.part_d;
         io.part_i = ws.part_i;
+        io.totals_f64 = ws.totals_f64 ? ws.totals_f64 + (int64_t)m * ix->n_classes : nullptr;
+        io.q8 = ws.q8;
+        io.qsc = ws.qsc;
+        io.cand = ws.cand;
+        io.upd_cls = ws.upd_cls;
+        io.upd_delta = ws.upd_delta;
         int rc = enqueue_batch(ix, plans[m], io, s, ev);
         if (rc) return rc;
         if (ev) {
@@ -531,8 +627,7 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
                                out_nbr_idx, out_nbr_dist);
     if (rc) return rc;
     if (n_images == 0) return LNBNN_OK;
-    if (mode == LNBNN_FP8_RERANK || mode == LNBNN_EXACT_I8)
-        return set_err(LNBNN_EINVAL, "mode %d is not built in this library", mode);
+    if (mode == LNBNN_EXACT_I8) return set_err(LNBNN_EINVAL, "mode %d is not built in this library", mode);
     std::lock_guard<std::mutex> lock(ix->mu);
     LN_HIP(hipSetDevice(ix->device));
     hipStream_t s = stream ? (hipStream_t)stream : ix->own_stream;
@@ -540,27 +635,32 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
     const bool per_image = flags & LNBNN_PER_IMAGE_LAUNCH;
     const bool timed = flags & LNBNN_TIMING;
     const int kp = k + 1;
+    const bool fp8 = mode == LNBNN_FP8_RERANK;
+    const int list_len = fp8 ? fp8_candidates(k) : kp;   // what the distance kernel keeps
     const int64_t n_q = img_offsets[n_images];
     const int64_t rb = row_bytes(dtype);
     const int64_t nc = ix->n_classes;
 
     Plan plan;
-    int64_t part = 0;
+    int64_t part = 0, q_max = 1;
     if (per_image) {
         for (int32_t m = 0; m < n_images; ++m) {
             Plan pm;
-            if ((rc = make_plan(ix, mode, kp, std::max<int64_t>(1, img_offsets[m + 1] - img_offsets[m]), -1, &pm)))
-                return rc;
+            const int64_t nm = std::max<int64_t>(1, img_offsets[m + 1] - img_offsets[m]);
+            if ((rc = make_plan(ix, mode, list_len, nm, -1, &pm))) return rc;
             part = std::max(part, part_elems(pm, pm.q_cap));
+            q_max = std::max(q_max, nm);
         }
     } else {
-        if ((rc = make_plan(ix, mode, kp, std::max<int64_t>(1, n_q), -1, &plan))) return rc;
+        if ((rc = make_plan(ix, mode, list_len, std::max<int64_t>(1, n_q), -1, &plan))) return rc;
         part = part_elems(plan, plan.q_cap);
+        q_max = plan.q_cap;
     }
     const bool want_nbr = out_nbr_idx != nullptr;
     if ((rc = ensure_ws(ix, ix->ws, std::max<int64_t>(1, n_q), n_images, part,
-                        (want_nbr && !dev) ? n_q * kp : 0, dev ? 0 : n_q * rb, false)))
+                        (want_nbr && !dev) ? n_q * kp : 0, dev ? 0 : n_q * rb, fp8)))
         return rc;
+    if (fp8 && (rc = ensure_fp8_ws(ix, ix->ws, q_max, list_len, k))) return rc;
     Workspace &ws = ix->ws;
 
     // the shared workspace may still be read by a call on another stream
@@ -600,6 +700,12 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
         io.nbr_dist = d_nbr_d;
         io.part_d = ws.part_d;
         io.part_i = ws.part_i;
+        io.totals_f64 = ws.totals_f64;
+        io.q8 = ws.q8;
+        io.qsc = ws.qsc;
+        io.cand = ws.cand;
+        io.upd_cls = ws.upd_cls;
+        io.upd_delta = ws.upd_delta;
         // timed calls launch directly: events recorded inside a captured
         // graph cannot be read back with hipEventElapsedTime
         if ((flags & LNBNN_NO_GRAPH) || timed) {
@@ -612,8 +718,8 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
 
     // outputs
     if (out_totals)
-        LN_HIP(hipMemcpyAsync(out_totals, ws.totals, (size_t)(n_images * nc * 8),
-                              dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+        LN_HIP(hipMemcpyAsync(out_totals, fp8 ? (const void *)ws.totals_f64 : (const void *)ws.totals,
+                              (size_t)(n_images * nc * 8), dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
     if (!dev) {
         LN_HIP(hipMemcpyAsync(out_class, ws.cls, (size_t)n_images * 4, hipMemcpyDeviceToHost, s));
         if (want_nbr) {
@@ -663,8 +769,10 @@ extern "C" int lnbnn_set_tuning(lnbnn_index *ix, int mode, int32_t k, const lnbn
     if (t->chunk_tiles < 0 || t->chunk_tiles % 8 != 0) return set_err(LNBNN_EINVAL, "chunk_tiles must be a multiple of 8");
     if (t->max_workgroups < 0) return set_err(LNBNN_EINVAL, "negative max_workgroups");
     const int fmt = mode_fmt(mode);
-    const int kpb = kp_bucket(k + 1, fmt);
-    if (t->variant >= 0 && !variant_supports(t->variant, fmt, k + 1))
+    const int list_len = mode == LNBNN_FP8_RERANK ? fp8_candidates(k) : k + 1;
+    const int kpb = kp_bucket(list_len, fmt);
+    if (kpb == 0) return set_err(LNBNN_EINVAL, "k = %d is not supported by mode %d", k, mode);
+    if (t->variant >= 0 && !variant_supports(t->variant, fmt, list_len))
         return set_err(LNBNN_EINVAL, "variant %d cannot serve k = %d", t->variant, k);
     std::lock_guard<std::mutex> lock(ix->mu);
     if (t->variant < 0 && t->chunk_tiles == 0 && t->max_workgroups == 0)
@@ -722,10 +830,9 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
     int rc = validate_classify(ix, queries_dev, dtype, img_offsets, n_images, k, mode, LNBNN_DEVICE_PTRS, true,
                                nullptr, nullptr);
     if (rc) return rc;
-    if (mode == LNBNN_FP8_RERANK || mode == LNBNN_EXACT_I8)
-        return set_err(LNBNN_EINVAL, "mode %d is not built in this library", mode);
+    if (mode == LNBNN_EXACT_I8) return set_err(LNBNN_EINVAL, "mode %d is not built in this library", mode);
     const int fmt = mode_fmt(mode);
-    const int kpb = kp_bucket(k + 1, fmt);
+    const int kpb = kp_bucket(mode == LNBNN_FP8_RERANK ? fp8_candidates(k) : k + 1, fmt);
     char arch[64] = "gfx";
     {
         hipDeviceProp_t prop;
@@ -736,7 +843,7 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
     if (cache_path) {
         auto m = read_cache(cache_path);
         auto it = m.find(key.str());
-        if (it != m.end() && variant_supports(it->second, fmt, k + 1)) {
+        if (it != m.end() && variant_supports(it->second, fmt, mode == LNBNN_FP8_RERANK ? fp8_candidates(k) : k + 1)) {
             std::lock_guard<std::mutex> lock(ix->mu);
             ix->pinned[{mode, kpb}] = lnbnn_tuning{it->second, 0, 0};
             if (best_variant) *best_variant = it->second;
@@ -749,8 +856,9 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
     LN_HIP(hipMalloc((void **)&d_cls, std::max<int32_t>(1, n_images) * 4));
     int best = -1;
     double best_ms = 1e30;
+    const int list_len = mode == LNBNN_FP8_RERANK ? fp8_candidates(k) : k + 1;
     for (int v = 0; v < num_variants(); ++v) {
-        if (!variant_supports(v, fmt, k + 1)) continue;
+        if (!variant_supports(v, fmt, list_len)) continue;
         if ((rc = lnbnn_set_variant(ix, mode, k, v))) break;
         double tot = 0;
         for (int rep = 0; rep < 3 && !rc; ++rep) {

@@ -11,6 +11,7 @@ constexpr int kDim = 128;
 constexpr int kTileRows = 32;            // rows of one MFMA A tile
 constexpr int kPadRows = 256;            // index rows are padded to this multiple
 constexpr int kMaxKP = 33;               // k + 1 <= 33
+constexpr int kMaxFp8K = 16;             // FP8 mode keeps 4k <= 64 candidates
 
 // Element formats of the packed reference tiles.
 enum Fmt { FMT_F16 = 0, FMT_BF16 = 1, FMT_FP8 = 2, FMT_I8 = 3 };
@@ -48,13 +49,36 @@ struct DistArgs {
     int32_t *part_i;
 };
 
+struct RerankArgs {
+    const BatchDesc *bd;
+    const int64_t *offsets;     // device [n_img + 1]
+    const float *qf32;          // f32 queries [n_q, 128]
+    const float *ref_f32;       // f32 references [n_refs, 128]
+    const int32_t *labels;
+    int64_t n_refs;
+    int32_t n_lists;            // 2 * n_slices
+    int32_t kp_stride;          // list length in the part buffers
+    int32_t n_cand;             // candidates kept per query (4k)
+    int32_t k;
+    int32_t n_classes;
+    int64_t q_cap;
+    const float *part_d;
+    const int32_t *part_i;
+    int32_t *cand;              // [q_cap, n_cand]
+    int32_t *upd_cls;           // [q_cap, k]: class of the update of rank j, -1 if none
+    double *upd_delta;          // [q_cap, k]
+    double *totals_f64;         // [n_img, n_classes]
+    int32_t *cls;               // [n_img]
+    int32_t *nbr_idx;           // [n_q, k+1] or null
+    float *nbr_dist;
+};
+
 struct FinishArgs {
-    const void *q;              // u8 queries (exact: for ||q||^2) or f32 queries (fp8)
+    const void *q;              // u8 queries (for ||q||^2)
     const BatchDesc *bd;
     const int64_t *offsets;     // device [n_img + 1]
     const int32_t *labels;      // [n_refs]
     int64_t n_refs;
-    const float *ref_f32;       // fp8 mode: FP32 references for the re-rank
     int32_t n_lists;            // 2 * n_slices
     int32_t kp_stride;          // list length in the part buffers
     int32_t k;
@@ -65,7 +89,6 @@ struct FinishArgs {
     unsigned long long *totals; // [n_img, n_classes] int64 (two's complement)
     int32_t *nbr_idx;           // [n_q, k+1] or null
     float *nbr_dist;            // [n_q, k+1] or null
-    int32_t fixed_point;        // fp8 mode: totals are fixed point * 2^40
 };
 
 // number of kernel variants and their parameters
@@ -78,10 +101,12 @@ int kp_bucket(int kp, int fmt);         // list length compiled for kp (0 = unsu
 // Upload-side packing.  refs_u8 / refs_f32 are device pointers.
 hipError_t launch_pack_u8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, int fmt,
                           uint4 *frag, float *seed, hipStream_t s);
-hipError_t launch_pack_f32_fp8(const float *refs, int64_t n_refs, int64_t n_pad,
-                               uint4 *frag, float *seed, int32_t *row_scale, hipStream_t s);
-hipError_t launch_quant_queries_fp8(const float *q, const BatchDesc *bd, int64_t q_cap,
-                                    uint8_t *q8, int32_t *q_scale, hipStream_t s);
+hipError_t launch_fp8_index(const float *refs, int64_t n_refs, int64_t n_pad, uint4 *frag, float *seed,
+                            int32_t *row_scale, hipStream_t s);
+hipError_t launch_fp8_qprep(const float *q, const BatchDesc *bd, int64_t q_cap, uint4 *q8, int32_t *qsc,
+                            hipStream_t s);
+hipError_t launch_rerank(const RerankArgs &a, int64_t q_cap, int64_t img_cap, hipStream_t s);
+int grid_for(int64_t n, int block, int cap);
 
 hipError_t launch_dist_topk(int variant, int fmt, int kp, const DistArgs &a, int grid,
                             hipStream_t s);
@@ -91,7 +116,6 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n_elems_cap, const Bat
                            int32_t n_classes, hipStream_t s);
 hipError_t launch_finish(const FinishArgs &a, int64_t q_cap, hipStream_t s);
 hipError_t launch_argmin(const unsigned long long *totals, const BatchDesc *bd, int64_t img_cap,
-                         int32_t n_classes, int32_t *out_class, double *totals_f64,
-                         int32_t fixed_point, hipStream_t s);
+                         int32_t n_classes, int32_t *out_class, hipStream_t s);
 
 }  // namespace lnbnn

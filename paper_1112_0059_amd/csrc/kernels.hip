@@ -2,10 +2,13 @@
 //
 // K0  pack        references -> MFMA A-fragment tiles + accumulator seeds
 // K1  dist_topk   distances on the matrix cores fused with top-(k+1)
-//                 selection in registers (Algorithm 2, NN(d_i, k+1))
+//                 selection in registers (Algorithm 2, NN(d_i, k+1)); in the
+//                 FP8 mode the same kernel keeps the 4k best candidates
 // K2  finish      merge of the per-slice lists, background distance,
 //                 per-class update of the image totals (Algorithm 2 body)
 // K3  argmin      per-image decision (Algorithm 2, return line)
+// (the FP8 packing, candidate merge, exact re-rank and per-image reduction
+// live in rerank.hip)
 //
 // Distances.  For a query q and reference r the kernels rank by
 //     d'(q, r) = ||r||^2 - 2 q.r  =  ||q - r||^2 - ||q||^2,
@@ -22,6 +25,7 @@ namespace lnbnn {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 static __device__ __forceinline__ uint32_t byte_at(uint2 r, int e)
 {
@@ -29,14 +33,28 @@ static __device__ __forceinline__ uint32_t byte_at(uint2 r, int e)
 }
 
 // ---------------------------------------------------------------------------
-// Operand policies.  A fragment step covers 16 elements of K for FP16/BF16
-// (v_mfma_f32_32x32x16_{f16,bf16}): lane l supplies row (l & 31) and K
-// elements 16*s + 8*(l >> 5) + e, e = 0..7, for both operands, so packing the
-// references and loading the queries with the same rule pairs them correctly.
+// Operand policies.
+//
+// FP16/BF16 (v_mfma_f32_32x32x16_{f16,bf16}): a K step covers 16 elements;
+// lane l supplies row (l & 31) and K elements 16*s + 8*(l >> 5) + e,
+// e = 0..7, for both operands (one uint4 per lane per step), so packing the
+// references and loading the queries with the same rule pairs them.
+//
+// FP8 (v_mfma_scale_f32_32x32x64_f8f6f4, OCP e4m3 operands): a K step
+// covers 64 elements; lane l supplies 32 bytes (two uint4) of row (l & 31),
+// K elements 64*s + 32*(l >> 5) + e.  Every lane also supplies an E8M0
+// scale (2^(v-127)) for its row; the hardware applies the scale of lane i to
+// bytes 0..15 and that of lane i+32 to bytes 16..31 of every lane of row i,
+// so a per-row scale must be (and is) supplied by both lanes of the row.
+// References carry 2^-e_r, queries 2^(1-e_q) on codes of -q * 2^e_q, so the
+// accumulator seeded with ||r~||^2 yields ||r~||^2 - 2 q~.r~ of the
+// dequantised values.
 // ---------------------------------------------------------------------------
 struct OpF16 {
     static constexpr int kFmt = FMT_F16;
     static constexpr int kSteps = 8;
+    static constexpr int kAU = 1;          // uint4 per lane per step
+    static constexpr bool kScaled = false;
     static __device__ __forceinline__ uint4 cvt8(uint2 raw, float mul)
     {
         f16x8 v;
@@ -44,16 +62,30 @@ struct OpF16 {
         for (int e = 0; e < 8; ++e) v[e] = (_Float16)(mul * (float)byte_at(raw, e));
         return __builtin_bit_cast(uint4, v);
     }
-    static __device__ __forceinline__ f32x16 mma(uint4 a, uint4 b, f32x16 c)
+    static __device__ __forceinline__ void load_b(const void *q, const int32_t *, int64_t qi, bool ok, int h,
+                                                  uint4 (&b)[kSteps][kAU], int &sb)
     {
-        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
-                                                      __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+        const uint8_t *qrow = static_cast<const uint8_t *>(q) + (ok ? qi : 0) * kDim + 8 * h;
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s) {
+            uint2 raw = make_uint2(0u, 0u);
+            if (ok) raw = *reinterpret_cast<const uint2 *>(qrow + 16 * s);
+            b[s][0] = cvt8(raw, -2.0f);
+        }
+        sb = 127;
+    }
+    static __device__ __forceinline__ f32x16 mma(const uint4 (&a)[kAU], const uint4 (&b)[kAU], f32x16 c, int, int)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a[0]),
+                                                      __builtin_bit_cast(f16x8, b[0]), c, 0, 0, 0);
     }
 };
 
 struct OpBF16 {
     static constexpr int kFmt = FMT_BF16;
     static constexpr int kSteps = 8;
+    static constexpr int kAU = 1;
+    static constexpr bool kScaled = false;
     static __device__ __forceinline__ uint4 cvt8(uint2 raw, float mul)
     {
         bf16x8 v;
@@ -61,16 +93,57 @@ struct OpBF16 {
         for (int e = 0; e < 8; ++e) v[e] = (__bf16)(mul * (float)byte_at(raw, e));
         return __builtin_bit_cast(uint4, v);
     }
-    static __device__ __forceinline__ f32x16 mma(uint4 a, uint4 b, f32x16 c)
+    static __device__ __forceinline__ void load_b(const void *q, const int32_t *, int64_t qi, bool ok, int h,
+                                                  uint4 (&b)[kSteps][kAU], int &sb)
     {
-        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
-                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+        const uint8_t *qrow = static_cast<const uint8_t *>(q) + (ok ? qi : 0) * kDim + 8 * h;
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s) {
+            uint2 raw = make_uint2(0u, 0u);
+            if (ok) raw = *reinterpret_cast<const uint2 *>(qrow + 16 * s);
+            b[s][0] = cvt8(raw, -2.0f);
+        }
+        sb = 127;
+    }
+    static __device__ __forceinline__ f32x16 mma(const uint4 (&a)[kAU], const uint4 (&b)[kAU], f32x16 c, int, int)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[0]),
+                                                       __builtin_bit_cast(bf16x8, b[0]), c, 0, 0, 0);
+    }
+};
+
+struct OpFP8 {
+    static constexpr int kFmt = FMT_FP8;
+    static constexpr int kSteps = 2;
+    static constexpr int kAU = 2;
+    static constexpr bool kScaled = true;
+    // queries: FP8 codes [n_q][128] in natural K order, E8M0 scale per query
+    static __device__ __forceinline__ void load_b(const void *q, const int32_t *qsc, int64_t qi, bool ok, int h,
+                                                  uint4 (&b)[kSteps][kAU], int &sb)
+    {
+        const uint4 *qrow = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(q) + (ok ? qi : 0) * kDim);
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s)
+#pragma unroll
+            for (int u = 0; u < kAU; ++u) b[s][u] = ok ? qrow[4 * s + 2 * h + u] : make_uint4(0u, 0u, 0u, 0u);
+        sb = ok ? qsc[qi] : 127;
+    }
+    static __device__ __forceinline__ f32x16 mma(const uint4 (&a)[kAU], const uint4 (&b)[kAU], f32x16 c, int sa,
+                                                 int sb)
+    {
+        i32x8 av, bv;
+        av[0] = (int)a[0].x; av[1] = (int)a[0].y; av[2] = (int)a[0].z; av[3] = (int)a[0].w;
+        av[4] = (int)a[1].x; av[5] = (int)a[1].y; av[6] = (int)a[1].z; av[7] = (int)a[1].w;
+        bv[0] = (int)b[0].x; bv[1] = (int)b[0].y; bv[2] = (int)b[0].z; bv[3] = (int)b[0].w;
+        bv[4] = (int)b[1].x; bv[5] = (int)b[1].y; bv[6] = (int)b[1].z; bv[7] = (int)b[1].w;
+        return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, c, 0, 0, 0, sa, 0, sb);
     }
 };
 
 // ---------------------------------------------------------------------------
-// K0: packing.  Fragment u = (tile * kSteps + s) * 64 + lane holds the eight
-// K elements lane `lane` supplies at step s for row 32*tile + (lane & 31).
+// K0: packing of u8 references.  Fragment u = (tile * kSteps + s) * 64 + lane
+// holds the eight K elements lane `lane` supplies at step s for row
+// 32*tile + (lane & 31).
 // ---------------------------------------------------------------------------
 template <class Op>
 __global__ void k_pack_u8(const uint8_t *__restrict__ refs, int64_t n_refs, int64_t n_frag,
@@ -122,11 +195,11 @@ __global__ void k_seed_u8(const uint8_t *__restrict__ refs, int64_t n_refs, int6
 // K1: distances + top-(k+1).
 //
 // Work item = (query block of W * 32 * NT queries, reference slice).
-// Each wave keeps 32*NT queries' -2q fragments in registers for the whole
-// slice; the workgroup streams 32-row reference tiles through a double-
-// buffered LDS stage of MT tiles.  With references as the MFMA M dimension
-// and queries as N, lane l's 16 accumulator registers are 16 references of
-// one query (column l & 31): register r is row 8*(r/4) + 4*(l/32) + r%4.
+// Each wave keeps 32*NT queries' operand fragments in registers; the
+// workgroup streams 32-row reference tiles through NB LDS stages of MT
+// tiles.  With references as the MFMA M dimension and queries as N, lane l's
+// 16 accumulator registers are 16 references of one query (column l & 31):
+// register r is row 8*(r/4) + 4*(l/32) + r%4.
 //
 // Selection.  Each lane keeps a sorted register list of the KP best
 // (d', index) pairs of its query among the rows it has seen (lanes l and
@@ -202,27 +275,28 @@ static __device__ __forceinline__ void tiles_select(const f32x16 (&acc)[NT], flo
 typedef __attribute__((address_space(1))) const void *gmem_ptr;
 typedef __attribute__((address_space(3))) void *lds_ptr;
 
-// Asynchronous copy of one LDS stage (MT tiles of fragments and their
-// seeds) straight from global memory into LDS (global_load_lds).  A
-// fragment instruction moves 64 lanes x 16 B to consecutive LDS addresses;
-// every wave also copies its share of the stage's MT*32 seeds with one
-// partial-lane 4-byte instruction.  Each wave therefore issues exactly
-// kStageLoads<MT, W> instructions per stage, which is what the vmcnt
-// waits below count on.
-template <int MT, int W>
+// Asynchronous copy of one LDS stage (MT tiles of fragments, their seeds
+// and, for scaled formats, their row scales) straight from global memory into
+// LDS (global_load_lds).  A fragment instruction moves 64 lanes x 16 B to
+// consecutive LDS addresses; every wave also copies its share of the
+// stage's MT*32 seeds (and scales) with one partial-lane 4-byte instruction.
+// Each wave therefore issues exactly StageLoads::total instructions per
+// stage, which is what the vmcnt waits count on.
+template <class Op, int MT, int W>
 struct StageLoads {
-    static constexpr int frag = MT * 8 / W;                 // 1 KB chunks per wave (8 per tile)
-    static constexpr int total = frag + 1;
-    static_assert(frag * W == MT * 8, "stage chunks must split evenly over the waves");
+    static constexpr int tile_chunks = Op::kSteps * Op::kAU;           // 1 KB chunks per tile
+    static constexpr int frag = MT * tile_chunks / W;                  // chunks per wave
+    static_assert(frag * W == MT * tile_chunks, "stage chunks must split evenly over the waves");
     static constexpr int seeds_per_wave = MT * kTileRows / W;
     static_assert(seeds_per_wave <= 64 && seeds_per_wave * W == MT * kTileRows, "seed split");
+    static constexpr int total = frag + 1 + (Op::kScaled ? 1 : 0);
 };
 
-template <int MT, int W, int TILE_U4>
-static __device__ __forceinline__ void stage_copy(const uint4 *src, uint4 *dst, const float *seed_src,
-                                                  float *seed_dst, int wave, int lane)
+template <class Op, int MT, int W, int TILE_U4>
+static __device__ __forceinline__ void stage_copy(const uint4 *src, uint4 *dst, const float *seed_src, float *seed_dst,
+                                                  const int32_t *rsc_src, int32_t *rsc_dst, int wave, int lane)
 {
-    using SL = StageLoads<MT, W>;
+    using SL = StageLoads<Op, MT, W>;
 #pragma unroll
     for (int c = 0; c < SL::frag; ++c) {
         const int chunk = c * W + wave;
@@ -231,6 +305,10 @@ static __device__ __forceinline__ void stage_copy(const uint4 *src, uint4 *dst, 
     const int s0 = wave * SL::seeds_per_wave;
     if (lane < SL::seeds_per_wave)
         __builtin_amdgcn_global_load_lds((gmem_ptr)(seed_src + s0 + lane), (lds_ptr)(seed_dst + s0), 4, 0, 0);
+    if constexpr (Op::kScaled) {
+        if (lane < SL::seeds_per_wave)
+            __builtin_amdgcn_global_load_lds((gmem_ptr)(rsc_src + s0 + lane), (lds_ptr)(rsc_dst + s0), 4, 0, 0);
+    }
 }
 
 // s_waitcnt with only the vector-memory counter limited (gfx9 encoding:
@@ -248,11 +326,13 @@ static __device__ __forceinline__ void wait_vmcnt()
 // Insertions for the previous tile (rare) follow after the block.
 template <class Op, int KP, int NT>
 static __device__ __forceinline__ void pipe_step(f32x16 (&acc_new)[NT], const f32x16 (&acc_old)[NT],
-                                                 const uint4 (&bq)[NT][Op::kSteps], const uint4 *frag,
-                                                 const float4 *seed, int lane, int h, float (&thr)[NT],
-                                                 float (&ld)[NT][KP], int (&li)[NT][KP], int row_old)
+                                                 const uint4 (&bq)[NT][Op::kSteps][Op::kAU], const int (&sb)[NT],
+                                                 const uint4 *frag, const float4 *seed, const int32_t *rsc, int lane,
+                                                 int h, float (&thr)[NT], float (&ld)[NT][KP], int (&li)[NT][KP],
+                                                 int row_old)
 {
     constexpr int S = Op::kSteps;
+    constexpr int AU = Op::kAU;
     f32x16 sd;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
@@ -262,18 +342,22 @@ static __device__ __forceinline__ void pipe_step(f32x16 (&acc_new)[NT], const f3
         sd[4 * g + 2] = sv.z;
         sd[4 * g + 3] = sv.w;
     }
-    uint4 av[S];
+    int sa = 127;
+    if constexpr (Op::kScaled) sa = rsc[lane & 31];
+    uint4 av[S][AU];
 #pragma unroll
-    for (int s = 0; s < S; ++s) av[s] = frag[s * 64 + lane];
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int u = 0; u < AU; ++u) av[s][u] = frag[(s * AU + u) * 64 + lane];
     bool any[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) any[nt] = __builtin_amdgcn_ballot_w64(min16(acc_old[nt]) < thr[nt]) != 0;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc_new[nt] = Op::mma(av[s], bq[nt][s], s == 0 ? sd : acc_new[nt]);
+        for (int nt = 0; nt < NT; ++nt) acc_new[nt] = Op::mma(av[s], bq[nt][s], s == 0 ? sd : acc_new[nt], sa, sb[nt]);
     }
-    __builtin_amdgcn_sched_group_barrier(0x100, S + 4, 0);     // LDS reads
+    __builtin_amdgcn_sched_group_barrier(0x100, S * AU + 4 + (Op::kScaled ? 1 : 0), 0);   // LDS reads
 #pragma unroll
     for (int i = 0; i < S * NT; ++i) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);     // one MFMA
@@ -289,16 +373,19 @@ __global__ __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W), amdgpu_wa
 void k_dist_topk(DistArgs a)
 {
     constexpr int S = Op::kSteps;
-    constexpr int TILE_U4 = S * 64;               // uint4 per 32-row tile
+    constexpr int AU = Op::kAU;
+    constexpr int TILE_U4 = S * AU * 64;          // uint4 per 32-row tile
     constexpr int STAGE_U4 = MT * TILE_U4;
     constexpr int QW = 32 * NT;                   // queries per wave
     constexpr int QB = W * QW;                    // queries per workgroup
     constexpr int PD = NB - 1;                    // stages in flight ahead of the one computed
-    constexpr int LPS = StageLoads<MT, W>::total; // loads per wave per stage
+    constexpr int LPS = StageLoads<Op, MT, W>::total;   // loads per wave per stage
+    constexpr int RSC = Op::kScaled ? MT * kTileRows : 1;
     static_assert(MT % 2 == 0, "tiles are processed in pairs");
     static_assert(NB >= 2 && (PD - 1) * LPS < 64, "prefetch depth");
     __shared__ uint4 s_frag[NB][STAGE_U4];
     __shared__ float4 s_seed[NB][MT * 8];
+    __shared__ int32_t s_rsc[NB][RSC];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -309,12 +396,12 @@ void k_dist_topk(DistArgs a)
     const int64_t n_items = n_qb * a.n_slices;
     const int n_chunks = (a.tiles_per_slice + a.chunk_tiles - 1) / a.chunk_tiles;
 
-    // Chunk-major walk: for every chunk of its slice, a workgroup runs all
-    // the (query block, slice) items it owns before moving to the next
-    // chunk, so the workgroups of an XCD stream the same few MB of
-    // references at about the same time and L2 serves them.  An item's
-    // neighbour lists live in registers while a chunk runs and in the
-    // partial-list buffer between chunks.
+    // Walk: for every chunk of its slice, a workgroup runs all the (query
+    // block, slice) items it owns before moving to the next chunk.  With the
+    // default chunk (the whole slice) each item is one sweep with its lists in
+    // registers; shorter chunks keep the workgroups of an XCD on the same
+    // references at the same time, with the lists parked in the partial-list
+    // buffer between chunks.
     for (int c = 0; c < n_chunks; ++c) {
         for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
             const int slice = (int)(item / n_qb);
@@ -326,19 +413,13 @@ void k_dist_topk(DistArgs a)
             const int64_t t1 = min(t0 + (int64_t)a.chunk_tiles, ts1);
             const int n_t = (int)(t1 - t0);           // multiple of 8, so of MT
 
-            uint4 bq[NT][S];
+            uint4 bq[NT][S][AU];
+            int sb[NT];
             int64_t qi[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 qi[nt] = qb * QB + wave * QW + nt * 32 + col;
-                const bool ok = qi[nt] < n_q;
-                const uint8_t *qrow = static_cast<const uint8_t *>(a.q) + (ok ? qi[nt] : 0) * kDim + 8 * h;
-#pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    uint2 raw = make_uint2(0u, 0u);
-                    if (ok) raw = *reinterpret_cast<const uint2 *>(qrow + 16 * s);
-                    bq[nt][s] = Op::cvt8(raw, -2.0f);
-                }
+                Op::load_b(a.q, a.q_scale, qi[nt], qi[nt] < n_q, h, bq[nt], sb[nt]);
             }
 
             float ld[NT][KP];
@@ -364,8 +445,9 @@ void k_dist_topk(DistArgs a)
 #pragma unroll
             for (int p = 0; p < PD; ++p) {
                 const int64_t ts = t0 + (int64_t)(p < n_st ? p : 0) * MT;
-                stage_copy<MT, W, TILE_U4>(a.frag + ts * TILE_U4, s_frag[p], a.seed + ts * kTileRows,
-                                           reinterpret_cast<float *>(s_seed[p]), wave, lane);
+                stage_copy<Op, MT, W, TILE_U4>(a.frag + ts * TILE_U4, s_frag[p], a.seed + ts * kTileRows,
+                                               reinterpret_cast<float *>(s_seed[p]), a.row_scale + ts * kTileRows,
+                                               s_rsc[p], wave, lane);
             }
             wait_vmcnt<(PD - 1) * LPS>();
             __syncthreads();
@@ -386,16 +468,20 @@ void k_dist_topk(DistArgs a)
                     const int sn = st + PD;
                     const int64_t ts = t0 + (int64_t)(sn < n_st ? sn : 0) * MT;
                     const int nb = (buf + PD) % NB;
-                    stage_copy<MT, W, TILE_U4>(a.frag + ts * TILE_U4, s_frag[nb], a.seed + ts * kTileRows,
-                                               reinterpret_cast<float *>(s_seed[nb]), wave, lane);
+                    stage_copy<Op, MT, W, TILE_U4>(a.frag + ts * TILE_U4, s_frag[nb], a.seed + ts * kTileRows,
+                                                   reinterpret_cast<float *>(s_seed[nb]),
+                                                   a.row_scale + ts * kTileRows, s_rsc[nb], wave, lane);
                 }
 #pragma unroll
                 for (int m = 0; m < MT; m += 2) {
                     const int row_t = (int)((t0 + (int64_t)st * MT + m) * kTileRows) + 4 * h;
-                    pipe_step<Op, KP, NT>(acc0, acc1, bq, s_frag[buf] + m * TILE_U4, s_seed[buf] + m * 8, lane, h,
-                                          thr, ld, li, row_prev);
-                    pipe_step<Op, KP, NT>(acc1, acc0, bq, s_frag[buf] + (m + 1) * TILE_U4,
-                                          s_seed[buf] + (m + 1) * 8, lane, h, thr, ld, li, row_t);
+                    pipe_step<Op, KP, NT>(acc0, acc1, bq, sb, s_frag[buf] + m * TILE_U4, s_seed[buf] + m * 8,
+                                          s_rsc[buf] + (Op::kScaled ? m * kTileRows : 0), lane, h, thr, ld, li,
+                                          row_prev);
+                    pipe_step<Op, KP, NT>(acc1, acc0, bq, sb, s_frag[buf] + (m + 1) * TILE_U4,
+                                          s_seed[buf] + (m + 1) * 8,
+                                          s_rsc[buf] + (Op::kScaled ? (m + 1) * kTileRows : 0), lane, h, thr, ld,
+                                          li, row_t);
                     row_prev = row_t + kTileRows;
                 }
                 wait_vmcnt<(PD - 1) * LPS>();   // stage st + 1 has landed (this wave's part)
@@ -510,8 +596,7 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs a)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_argmin(const unsigned long long *__restrict__ totals,
                                                 const BatchDesc *bd, int32_t n_classes,
-                                                int32_t *__restrict__ out_class,
-                                                double *__restrict__ totals_f64, int32_t fixed_point)
+                                                int32_t *__restrict__ out_class)
 {
     const int lane = threadIdx.x & 63;
     const int64_t n_img = bd->n_img;
@@ -525,7 +610,6 @@ __global__ __launch_bounds__(256) void k_argmin(const unsigned long long *__rest
                 best = v;
                 bc = c;
             }
-            if (totals_f64) totals_f64[img * n_classes + c] = (double)v * 0x1p-40;
         }
         for (int off = 32; off > 0; off >>= 1) {
             const long long ov = __shfl_xor(best, off);
@@ -537,7 +621,6 @@ __global__ __launch_bounds__(256) void k_argmin(const unsigned long long *__rest
         }
         if (lane == 0) out_class[img] = bc;
     }
-    (void)fixed_point;
 }
 
 __global__ void k_fill_u64(unsigned long long *p, const BatchDesc *bd, int32_t n_classes, int64_t cap)
@@ -572,10 +655,15 @@ const char *variant_name(int v) { return (v >= 0 && v < kNumVariants) ? kVariant
 
 int kp_bucket(int kp, int fmt)
 {
-    if (fmt != FMT_F16 && fmt != FMT_BF16) return 0;
-    static const int b[] = {2, 6, 11, 16, 21, 33};
-    for (int x : b)
-        if (kp <= x) return x;
+    if (fmt == FMT_F16 || fmt == FMT_BF16) {
+        static const int b[] = {2, 6, 11, 16, 21, 33};
+        for (int x : b)
+            if (kp <= x) return x;
+    } else if (fmt == FMT_FP8) {
+        static const int b[] = {4, 8, 20, 40, 64};   // candidate-list lengths (4k)
+        for (int x : b)
+            if (kp <= x) return x;
+    }
     return 0;
 }
 
@@ -584,6 +672,7 @@ bool variant_supports(int v, int fmt, int kp)
     if (v < 0 || v >= kNumVariants) return false;
     const int b = kp_bucket(kp, fmt);
     if (b == 0) return false;
+    if (fmt == FMT_FP8) return v == 0 || v == 6 || (v == 4 && b <= 20);
     return kVariants[v].nt == 1 || b <= 16;
 }
 
@@ -600,7 +689,11 @@ static void *pick_variant(int v)
     case 0: return kernel_ptr<Op, KP, 1, 2, 4, 4>();
     case 6: return kernel_ptr<Op, KP, 1, 4, 8, 4>();
     }
-    if constexpr (KP <= 16) {
+    if constexpr (Op::kFmt == FMT_FP8) {
+        if constexpr (KP <= 20) {
+            if (v == 4) return kernel_ptr<Op, KP, 2, 4, 8, 4>();
+        }
+    } else if constexpr (KP <= 16) {
         switch (v) {
         case 1: return kernel_ptr<Op, KP, 2, 2, 4, 4>();
         case 2: return kernel_ptr<Op, KP, 2, 4, 4, 2>();
@@ -616,13 +709,23 @@ static void *pick_variant(int v)
 template <class Op>
 static void *pick_kp(int v, int kpb)
 {
-    switch (kpb) {
-    case 2: return pick_variant<Op, 2>(v);
-    case 6: return pick_variant<Op, 6>(v);
-    case 11: return pick_variant<Op, 11>(v);
-    case 16: return pick_variant<Op, 16>(v);
-    case 21: return pick_variant<Op, 21>(v);
-    case 33: return pick_variant<Op, 33>(v);
+    if constexpr (Op::kFmt == FMT_FP8) {
+        switch (kpb) {
+        case 4: return pick_variant<Op, 4>(v);
+        case 8: return pick_variant<Op, 8>(v);
+        case 20: return pick_variant<Op, 20>(v);
+        case 40: return pick_variant<Op, 40>(v);
+        case 64: return pick_variant<Op, 64>(v);
+        }
+    } else {
+        switch (kpb) {
+        case 2: return pick_variant<Op, 2>(v);
+        case 6: return pick_variant<Op, 6>(v);
+        case 11: return pick_variant<Op, 11>(v);
+        case 16: return pick_variant<Op, 16>(v);
+        case 21: return pick_variant<Op, 21>(v);
+        case 33: return pick_variant<Op, 33>(v);
+        }
     }
     return nullptr;
 }
@@ -634,6 +737,7 @@ static void *dist_kernel(int v, int fmt, int kp)
     switch (fmt) {
     case FMT_F16: return pick_kp<OpF16>(v, b);
     case FMT_BF16: return pick_kp<OpBF16>(v, b);
+    case FMT_FP8: return pick_kp<OpFP8>(v, b);
     }
     return nullptr;
 }
@@ -659,7 +763,7 @@ int dist_topk_blocks_per_cu(int v, int fmt, int kp)
 // ---------------------------------------------------------------------------
 // Host launchers of the small kernels
 // ---------------------------------------------------------------------------
-static int grid_for(int64_t n, int block, int cap = 65536)
+int grid_for(int64_t n, int block, int cap)
 {
     int64_t g = (n + block - 1) / block;
     if (g < 1) g = 1;
@@ -672,15 +776,15 @@ hipError_t launch_pack_u8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, in
 {
     const int64_t n_frag = (n_pad / kTileRows) * 8 * 64;
     if (fmt == FMT_F16)
-        k_pack_u8<OpF16><<<grid_for(n_frag, 256), 256, 0, s>>>(refs, n_refs, n_frag, frag);
+        k_pack_u8<OpF16><<<grid_for(n_frag, 256, 65536), 256, 0, s>>>(refs, n_refs, n_frag, frag);
     else if (fmt == FMT_BF16)
-        k_pack_u8<OpBF16><<<grid_for(n_frag, 256), 256, 0, s>>>(refs, n_refs, n_frag, frag);
+        k_pack_u8<OpBF16><<<grid_for(n_frag, 256, 65536), 256, 0, s>>>(refs, n_refs, n_frag, frag);
     else
         return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (seed) {
-        k_seed_u8<<<grid_for(n_pad, 256), 256, 0, s>>>(refs, n_refs, n_pad, seed);
+        k_seed_u8<<<grid_for(n_pad, 256, 65536), 256, 0, s>>>(refs, n_refs, n_pad, seed);
         e = hipGetLastError();
     }
     return e;
@@ -700,23 +804,10 @@ hipError_t launch_finish(const FinishArgs &a, int64_t q_cap, hipStream_t s)
 }
 
 hipError_t launch_argmin(const unsigned long long *totals, const BatchDesc *bd, int64_t img_cap,
-                         int32_t n_classes, int32_t *out_class, double *totals_f64, int32_t fixed_point,
-                         hipStream_t s)
+                         int32_t n_classes, int32_t *out_class, hipStream_t s)
 {
-    k_argmin<<<grid_for(img_cap, 4, 16384), 256, 0, s>>>(totals, bd, n_classes, out_class, totals_f64,
-                                                          fixed_point);
+    k_argmin<<<grid_for(img_cap, 4, 16384), 256, 0, s>>>(totals, bd, n_classes, out_class);
     return hipGetLastError();
-}
-
-hipError_t launch_pack_f32_fp8(const float *, int64_t, int64_t, uint4 *, float *, int32_t *, hipStream_t)
-{
-    return hipErrorNotSupported;
-}
-
-hipError_t launch_quant_queries_fp8(const float *, const BatchDesc *, int64_t, uint8_t *, int32_t *,
-                                    hipStream_t)
-{
-    return hipErrorNotSupported;
 }
 
 }  // namespace lnbnn

@@ -46,6 +46,15 @@ struct Workspace {
     int32_t *cls = nullptr;
     int32_t *nbr_idx = nullptr;
     float *nbr_dist = nullptr;
+    // FP8 mode
+    int64_t q8_cap = 0;         // queries
+    int64_t cand_cap = 0;       // elements of cand
+    int64_t upd_cap = 0;        // elements of upd_cls / upd_delta
+    uint4 *q8 = nullptr;        // [q8_cap, 8] FP8 codes
+    int32_t *qsc = nullptr;     // [q8_cap] E8M0 query scales
+    int32_t *cand = nullptr;
+    int32_t *upd_cls = nullptr;
+    double *upd_delta = nullptr;
     int device = 0;
     ~Workspace();
     int64_t bytes() const;
@@ -78,6 +87,12 @@ struct BatchIO {
     float *nbr_dist = nullptr;
     float *part_d = nullptr;
     int32_t *part_i = nullptr;
+    // FP8 mode
+    uint4 *q8 = nullptr;
+    int32_t *qsc = nullptr;
+    int32_t *cand = nullptr;
+    int32_t *upd_cls = nullptr;
+    double *upd_delta = nullptr;
 };
 
 struct GraphEntry {
@@ -102,7 +117,8 @@ struct lnbnn_index {
     uint4 *frag[4] = {nullptr, nullptr, nullptr, nullptr};
     float *seed[4] = {nullptr, nullptr, nullptr, nullptr};
     int32_t *labels = nullptr;
-    float *ref_f32 = nullptr;
+    float *ref_f32 = nullptr;       // FP8 mode: FP32 references for the re-rank
+    int32_t *row_scale = nullptr;   // FP8 mode: E8M0 exponent of every padded row
     int64_t device_bytes = 0;
 
     std::mutex mu;                                     // classify path
@@ -131,6 +147,8 @@ int64_t part_elems(const Plan &p, int64_t q_cap);
 int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t s, hipEvent_t *ev);
 int ensure_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int64_t img_cap, int64_t part,
               int64_t nbr, int64_t qbytes, bool need_f64);
+int ensure_fp8_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int n_cand, int k);
+int fp8_candidates(int k);
 int64_t row_bytes(int dtype);
 
 void server_stop(lnbnn_index *ix);

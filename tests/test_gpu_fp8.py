@@ -1,0 +1,205 @@
+"""FP8 candidate pass + exact FP32 re-rank (float descriptors) against the
+FP64 oracle.
+
+The FP8 pass only chooses 4k candidates; parity is therefore stated as
+quality (neighbour recall, decisions) plus, wherever a descriptor's k+1
+neighbours match the oracle's, a rounding bound on its contribution to the
+totals:  the re-rank sums 128 FP32 terms (q_t - r_t)^2 sequentially, so each
+distance carries a relative error below GAMMA = 130 * 2^-24, and an update
+dist_C - dist_B is off by at most GAMMA * (dist_C + dist_B).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1112_0059_amd as L
+import synth
+
+pytestmark = pytest.mark.gpu
+FP8 = L.LNBNN_FP8_RERANK
+GAMMA = 130 * 2.0 ** -24
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _problem(seed=0, n_classes=8, n_train=4, n_desc=300, n_img=16, q=(200, 400)):
+    cfg = synth.scaled(synth.CONFIGS["P"], n_classes=n_classes, n_train=n_train, n_desc=n_desc,
+                       n_img=n_img, q_lo=q[0], q_hi=q[1], index_seed=5000 + seed, query_seed=6000 + seed)
+    R, labels = synth.gen_index(cfg)
+    Q, off, true_cls = synth.gen_queries(cfg)
+    return cfg, R, labels, Q, off, true_cls
+
+
+def _bound_per_image(wi, wd, labels, off, k, n_classes):
+    """Upper bound on |T_gpu - T_oracle| per (image, class) when the
+    neighbour lists match: sum of GAMMA * (dist_C + dist_B) over updates."""
+    n_img = len(off) - 1
+    B = np.zeros((n_img, n_classes))
+    for m in range(n_img):
+        for i in range(off[m], off[m + 1]):
+            seen = set()
+            for j in range(k):
+                c = labels[wi[i, j]]
+                if c in seen:
+                    continue
+                seen.add(c)
+                B[m, c] += GAMMA * (wd[i, j] + wd[i, k])
+    return B
+
+
+def _compare(got, want, labels, off, k, n_classes, min_recall=0.995):
+    cls, tot, ni, nd = got
+    wt, wc, wi, wd = want
+    kp = k + 1
+    recall = np.mean([len(set(ni[i]) & set(wi[i])) / kp for i in range(ni.shape[0])])
+    same = np.all(ni == wi, axis=1)
+    _say(f"recall {recall:.5f}, identical lists {same.mean():.4f}")
+    assert recall >= min_recall
+    # distances of matching lists: FP32 re-rank within the rounding bound
+    rel = np.abs(nd[same].astype(np.float64) - wd[same]) / np.maximum(wd[same], 1e-30)
+    assert np.all(rel <= GAMMA), rel.max()
+    # totals of images whose every list matches the oracle's
+    B = _bound_per_image(wi, wd, labels, off, k, n_classes)
+    n_checked = 0
+    for m in range(len(off) - 1):
+        if np.all(same[off[m]:off[m + 1]]):
+            n_checked += 1
+            assert np.all(np.abs(tot[m] - wt[m]) <= B[m] + 1e-12), m
+    # decisions: must agree wherever the oracle's margin exceeds the bound
+    for m in range(len(off) - 1):
+        if cls[m] != wc[m]:
+            margin = np.sort(wt[m])[1] - np.sort(wt[m])[0]
+            assert not np.all(same[off[m]:off[m + 1]]) or margin <= 2 * B[m].max(), m
+    agree = np.mean(cls == wc)
+    _say(f"decision agreement {agree:.4f}, images with all lists identical {n_checked}/{len(off) - 1}")
+    return recall, agree
+
+
+@pytest.fixture(scope="module")
+def small():
+    cfg, R, labels, Q, off, true_cls = _problem()
+    ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(FP8))
+    want = {k: oracle.classify(Q, R, labels, cfg.n_classes, off, k) for k in (1, 5, 10)}
+    yield cfg, R, labels, Q, off, ix, want
+    ix.free()
+
+
+@pytest.mark.parametrize("k", [1, 5, 10])
+def test_fp8_small_quality(small, k):
+    cfg, R, labels, Q, off, ix, want = small
+    _say(f"fp8 small k={k}")
+    got = L.lnbnn_classify(ix, Q, off, k, FP8, want_neighbours=True)
+    _check_mechanics(Q, R, got, k)
+    # 4k candidates: at k = 1 only 4 of them stand behind the top 2
+    _, agree = _compare(got, want[k], labels, off, k, cfg.n_classes, min_recall=0.99 if k == 1 else 0.995)
+    assert agree == 1.0
+
+
+@pytest.mark.parametrize("flags", [L.LNBNN_NO_GRAPH, L.LNBNN_PER_IMAGE_LAUNCH, L.LNBNN_TIMING])
+def test_fp8_launch_forms_identical(small, flags):
+    """Every launch form gives bit-identical results (per-image launches use
+    other slice splits: results may not depend on them)."""
+    cfg, R, labels, Q, off, ix, want = small
+    base = L.lnbnn_classify(ix, Q, off, 10, FP8, want_neighbours=True)
+    got = L.lnbnn_classify(ix, Q, off, 10, FP8, flags=flags, want_neighbours=True)
+    for x, y in zip(base, got):
+        assert np.array_equal(x, y)
+
+
+def test_fp8_alone_equals_in_mix(small):
+    """An image classified alone gives bit-for-bit the totals, class and
+    neighbours it gets inside a batch."""
+    cfg, R, labels, Q, off, ix, want = small
+    batch = L.lnbnn_classify(ix, Q, off, 10, FP8, want_neighbours=True)
+    for m in (0, 7, 15):
+        s, e = off[m], off[m + 1]
+        alone = L.lnbnn_classify(ix, Q[s:e], np.array([0, e - s], np.int64), 10, FP8, want_neighbours=True)
+        assert alone[0][0] == batch[0][m]
+        assert np.array_equal(alone[1][0], batch[1][m])
+        assert np.array_equal(alone[2], batch[2][s:e]) and np.array_equal(alone[3], batch[3][s:e])
+
+
+@pytest.mark.parametrize("variant", [0, 6])
+def test_fp8_variants_and_chunks(small, variant):
+    cfg, R, labels, Q, off, ix, want = small
+    base = L.lnbnn_classify(ix, Q, off, 10, FP8, want_neighbours=True)
+    L.lnbnn_set_tuning(ix, FP8, 10, variant=variant, chunk_tiles=8, max_workgroups=3)
+    try:
+        got = L.lnbnn_classify(ix, Q, off, 10, FP8, want_neighbours=True)
+    finally:
+        L.lnbnn_set_tuning(ix, FP8, 10)
+    for x, y in zip(base, got):
+        assert np.array_equal(x, y)
+
+
+def test_fp8_device_pointers(small):
+    import torch
+    cfg, R, labels, Q, off, ix, want = small
+    host = L.lnbnn_classify(ix, Q, off, 5, FP8, want_neighbours=True)
+    dq = torch.from_numpy(Q).cuda()
+    for rep in range(3):
+        got = L.lnbnn_classify(ix, dq, off, 5, FP8, want_neighbours=True)
+        torch.cuda.synchronize()
+        for x, y in zip(host, got):
+            assert np.array_equal(x, y.cpu().numpy())
+
+
+def _check_mechanics(Q, R, got, k):
+    """Whatever the candidates, every returned neighbour carries its true
+    distance (FP32 re-rank within GAMMA of FP64) and lists are in
+    (distance, index) order."""
+    _, _, ni, nd = got
+    for i in range(ni.shape[0]):
+        diff = R[ni[i]].astype(np.float64) - Q[i].astype(np.float64)[None, :]
+        d64 = np.sum(diff * diff, axis=1)
+        assert np.all(np.abs(nd[i] - d64) <= GAMMA * d64 + 1e-30), i
+        ok = (np.diff(nd[i]) > 0) | ((np.diff(nd[i]) == 0) & (np.diff(ni[i]) > 0))
+        assert np.all(ok), i
+
+
+def test_fp8_edge_cases():
+    """Ragged reference count, 4k == n_refs (every reference is a candidate,
+    so the result must equal the oracle's), all-zero rows, empty images.
+    Unstructured random vectors are nearly equidistant, the hardest case for
+    an FP8 shortlist, so recall is only bounded loosely there."""
+    rng = np.random.default_rng(3)
+    for n_refs, k, min_recall in ((1000 + 7, 10, 0.95), (40, 10, 1.0), (12, 3, 1.0)):
+        R = np.maximum(rng.standard_normal((n_refs, 128)), 0).astype(np.float32)
+        R[::17] = 0.0
+        labels = rng.integers(0, 5, size=n_refs).astype(np.int32)
+        Q = np.maximum(rng.standard_normal((150, 128)), 0).astype(np.float32)
+        Q[3] = 0.0
+        Q[10] = R[5]
+        off = np.array([0, 0, 70, 150, 150], np.int64)
+        _say(f"fp8 edge n_refs={n_refs} k={k}")
+        want = oracle.classify(Q, R, labels, 6, off, k)
+        ix = L.lnbnn_build_index(R, labels, 6, L.LNBNN_MODE_BIT(FP8))
+        try:
+            got = L.lnbnn_classify(ix, Q, off, k, FP8, want_neighbours=True)
+        finally:
+            ix.free()
+        _check_mechanics(Q, R, got, k)
+        _compare(got, want, labels, off, k, 6, min_recall=min_recall)
+        assert got[0][0] == 0 and np.all(got[1][0] == 0) and np.all(got[1][3] == 0)
+
+
+def test_fp8_rejects():
+    R = np.zeros((100, 128), np.float32)
+    lab = np.zeros(100, np.int32)
+    ix = L.lnbnn_build_index(R, lab, 1, L.LNBNN_MODE_BIT(FP8))
+    try:
+        with pytest.raises(L.LnbnnError):
+            L.lnbnn_classify(ix, R[:3], np.array([0, 3], np.int64), 17, FP8)      # k > 16
+        with pytest.raises(L.LnbnnError):
+            L.lnbnn_classify(ix, R[:3], np.array([0, 3], np.int64), 5, L.LNBNN_EXACT_F16)
+        with pytest.raises(L.LnbnnError):
+            L.lnbnn_classify(ix, R[:3].astype(np.uint8), np.array([0, 3], np.int64), 5, FP8)
+    finally:
+        ix.free()
+    with pytest.raises(L.LnbnnError):
+        L.lnbnn_build_index(R, lab, 1, L.LNBNN_MODE_BIT(L.LNBNN_EXACT_F16))
