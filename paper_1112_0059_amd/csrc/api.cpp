@@ -91,13 +91,14 @@ static int grow(void **p, int64_t have, int64_t need, size_t elem)
     return LNBNN_OK;
 }
 
-static void drop_graphs(lnbnn_index *ix)
+void drop_graphs(std::map<std::string, GraphEntry> &graphs)
 {
-    for (auto &kv : ix->graphs) {
+    for (auto &kv : graphs)
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
-    }
-    ix->graphs.clear();
+    graphs.clear();
 }
+
+static void drop_graphs(lnbnn_index *ix) { drop_graphs(ix->graphs); }
 
 int ensure_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int64_t img_cap, int64_t part, int64_t nbr,
               int64_t qbytes, bool need_f64)
@@ -167,10 +168,14 @@ int ensure_fp8_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int n_cand, int
 static int blocks_per_cu(lnbnn_index *ix, int v, int fmt, int kpb)
 {
     auto key = std::make_tuple(v, fmt, kpb);
-    auto it = ix->occupancy.find(key);
-    if (it != ix->occupancy.end()) return it->second;
+    {
+        std::lock_guard<std::mutex> lock(ix->plan_mu);
+        auto it = ix->occupancy.find(key);
+        if (it != ix->occupancy.end()) return it->second;
+    }
     int n = dist_topk_blocks_per_cu(v, fmt, kpb);
     if (n < 1) n = 1;
+    std::lock_guard<std::mutex> lock(ix->plan_mu);
     ix->occupancy[key] = n;
     return n;
 }
@@ -191,8 +196,11 @@ int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_varia
     const int kpb = kp_bucket(kp, fmt);
     if (kpb == 0) return set_err(LNBNN_EINVAL, "k + 1 = %d is not supported by mode %d", kp, mode);
     lnbnn_tuning tu{-1, 0, 0};
-    auto it = ix->pinned.find({mode, kpb});
-    if (it != ix->pinned.end()) tu = it->second;
+    {
+        std::lock_guard<std::mutex> lock(ix->plan_mu);
+        auto it = ix->pinned.find({mode, kpb});
+        if (it != ix->pinned.end()) tu = it->second;
+    }
     int v = forced_variant >= 0 ? forced_variant : tu.variant;
     if (v < 0) v = default_variant(fmt, kp);
     if (!variant_supports(v, fmt, kp))
@@ -523,7 +531,7 @@ static int validate_classify(const lnbnn_index *ix, const void *queries, int dty
     return LNBNN_OK;
 }
 
-static std::string graph_key(const Plan &p, const BatchIO &io)
+std::string lnbnn::graph_key(const Plan &p, const BatchIO &io)
 {
     std::ostringstream o;
     o << p.variant << '/' << p.fmt << '/' << p.kpb << '/' << p.n_slices << '/' << p.tiles_per_slice << '/' << p.chunk_tiles << '/'
@@ -534,11 +542,12 @@ static std::string graph_key(const Plan &p, const BatchIO &io)
 }
 
 // Replay (capturing on first use) the launch sequence of a batch.
-static int launch_graph(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t s)
+int lnbnn::launch_graph(std::map<std::string, GraphEntry> &graphs, lnbnn_index *ix, const Plan &p, const BatchIO &io,
+                 hipStream_t s)
 {
     const std::string key = graph_key(p, io);
-    auto it = ix->graphs.find(key);
-    if (it == ix->graphs.end()) {
+    auto it = graphs.find(key);
+    if (it == graphs.end()) {
         GraphEntry g;
         LN_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         int rc = enqueue_batch(ix, p, io, s, nullptr);
@@ -552,7 +561,7 @@ static int launch_graph(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipSt
         e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return hip_err(e, "hipGraphInstantiate");
-        it = ix->graphs.emplace(key, g).first;
+        it = graphs.emplace(key, g).first;
     }
     LN_HIP(hipGraphLaunch(it->second.exec, s));
     return LNBNN_OK;
@@ -712,7 +721,7 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
             if (timed) ev = ix->tev;
             if ((rc = enqueue_batch(ix, plan, io, s, ev))) return rc;
         } else {
-            if ((rc = launch_graph(ix, plan, io, s))) return rc;
+            if ((rc = launch_graph(ix->graphs, ix, plan, io, s))) return rc;
         }
     }
 
@@ -774,7 +783,7 @@ extern "C" int lnbnn_set_tuning(lnbnn_index *ix, int mode, int32_t k, const lnbn
     if (kpb == 0) return set_err(LNBNN_EINVAL, "k = %d is not supported by mode %d", k, mode);
     if (t->variant >= 0 && !variant_supports(t->variant, fmt, list_len))
         return set_err(LNBNN_EINVAL, "variant %d cannot serve k = %d", t->variant, k);
-    std::lock_guard<std::mutex> lock(ix->mu);
+    std::lock_guard<std::mutex> lock(ix->plan_mu);
     if (t->variant < 0 && t->chunk_tiles == 0 && t->max_workgroups == 0)
         ix->pinned.erase({mode, kpb});
     else
@@ -844,7 +853,7 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
         auto m = read_cache(cache_path);
         auto it = m.find(key.str());
         if (it != m.end() && variant_supports(it->second, fmt, mode == LNBNN_FP8_RERANK ? fp8_candidates(k) : k + 1)) {
-            std::lock_guard<std::mutex> lock(ix->mu);
+            std::lock_guard<std::mutex> lock(ix->plan_mu);
             ix->pinned[{mode, kpb}] = lnbnn_tuning{it->second, 0, 0};
             if (best_variant) *best_variant = it->second;
             return LNBNN_OK;

@@ -121,7 +121,8 @@ struct lnbnn_index {
     int32_t *row_scale = nullptr;   // FP8 mode: E8M0 exponent of every padded row
     int64_t device_bytes = 0;
 
-    std::mutex mu;                                     // classify path
+    std::mutex mu;                                     // classify path (workspace, graphs)
+    std::mutex plan_mu;                                // tuning and occupancy caches
     lnbnn::Workspace ws;
     std::map<std::pair<int, int>, lnbnn_tuning> pinned;   // (mode, kp bucket) -> launch tuning
     std::map<std::tuple<int, int, int>, int> occupancy;  // (variant, fmt, kpb) -> blocks/CU
@@ -150,6 +151,11 @@ int ensure_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int64_t img_cap, in
 int ensure_fp8_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int n_cand, int k);
 int fp8_candidates(int k);
 int64_t row_bytes(int dtype);
+
+int launch_graph(std::map<std::string, GraphEntry> &graphs, lnbnn_index *ix, const Plan &p, const BatchIO &io,
+                 hipStream_t s);
+void drop_graphs(std::map<std::string, GraphEntry> &graphs);
+std::string graph_key(const Plan &p, const BatchIO &io);
 
 void server_stop(lnbnn_index *ix);
 bool server_pending(lnbnn_index *ix);
