@@ -32,7 +32,7 @@ PEAK_MFMA_F16_TFLOPS = 2500.0       # MI355X dense FP16/BF16 matrix peak
 PEAK_MFMA_FP8_TFLOPS = 5000.0       # MI355X dense FP8 matrix peak
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dist_topk_L_k10_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1112_0059_amd", "csrc", "kernels.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_1112_0059_amd", "csrc", f) for f in ("dist_topk.h", "dist_inst.hip")]
 TUNING_CACHE = os.path.join(ROOT, "paper_1112_0059_amd", "tuning_cache.json")
 
 
@@ -41,8 +41,12 @@ def log(*a):
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the distance kernel's sources (template + instance unit)."""
+    h = hashlib.sha256()
+    for p in KERNEL_SRC:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_per_launch():

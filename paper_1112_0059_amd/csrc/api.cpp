@@ -77,8 +77,13 @@ int64_t Workspace::bytes() const
            nbr_cap * 8 + img_cap * 4 + q8_cap * (kDim + 4) + cand_cap * 4 + upd_cap * 12;
 }
 
-// FP8 mode keeps 4k candidates per query (at least k + 1).
+// FP8 mode re-ranks 4k candidates per query (at least k + 1).  The
+// distance kernel keeps, per half-lane list, the best 2k FP8 keys (rounded
+// up to a compiled list length); the two halves see disjoint rows, so the
+// union of a query's lists holds at least its 4k best keys' first 2k and
+// the 4k candidates are the best 4k of that union.
 int fp8_candidates(int k) { return 4 * k; }
+int dist_list_len(int mode, int k) { return mode == LNBNN_FP8_RERANK ? 2 * k : k + 1; }
 
 static int grow(void **p, int64_t have, int64_t need, size_t elem)
 {
@@ -240,6 +245,13 @@ int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t
 {
     if (fault_injected("launch")) return set_err(LNBNN_EDEVICE, "injected launch failure");
     const bool fp8 = p.fmt == FMT_FP8;
+    // every buffer the launches write must hold what this plan writes
+    const Workspace *w = io.ws;
+    if (!w || io.q_cap > w->q_cap || io.img_cap > w->img_cap || part_elems(p, io.q_cap) > w->part_cap)
+        return set_err(LNBNN_EINVAL, "internal: workspace smaller than the plan");
+    if (fp8 && (io.q_cap > w->q8_cap || io.q_cap * fp8_candidates(io.k) > w->cand_cap ||
+                io.q_cap * io.k > w->upd_cap))
+        return set_err(LNBNN_EINVAL, "internal: FP8 workspace smaller than the plan");
     if (ev) LN_HIP(hipEventRecord(ev[2], s));
     if (fp8)
         LN_HIP(launch_fp8_qprep(static_cast<const float *>(io.q), io.bd, io.q_cap, io.q8, io.qsc, s));
@@ -573,7 +585,8 @@ static int classify_per_image(lnbnn_index *ix, const void *dq, const int64_t *of
 {
     Workspace &ws = ix->ws;
     const int kp = k + 1;
-    const int list_len = mode == LNBNN_FP8_RERANK ? fp8_candidates(k) : kp;
+    (void)kp;
+    const int list_len = dist_list_len(mode, k);
     std::vector<Plan> plans(n_images);
     for (int32_t m = 0; m < n_images; ++m) {
         int rc = make_plan(ix, mode, list_len, std::max<int64_t>(1, off[m + 1] - off[m]), -1, &plans[m]);
@@ -604,6 +617,7 @@ static int classify_per_image(lnbnn_index *ix, const void *dq, const int64_t *of
         io.totals = ws.totals + (int64_t)m * ix->n_classes;
         io.nbr_idx = nbr_idx ? nbr_idx + off[m] * kp : nullptr;
         io.nbr_dist = nbr_dist ? nbr_dist + off[m] * kp : nullptr;
+        io.ws = &ws;
         io.part_d = ws.part_d;
         io.part_i = ws.part_i;
         io.totals_f64 = ws.totals_f64 ? ws.totals_f64 + (int64_t)m * ix->n_classes : nullptr;
@@ -645,7 +659,7 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
     const bool timed = flags & LNBNN_TIMING;
     const int kp = k + 1;
     const bool fp8 = mode == LNBNN_FP8_RERANK;
-    const int list_len = fp8 ? fp8_candidates(k) : kp;   // what the distance kernel keeps
+    const int list_len = dist_list_len(mode, k);   // what the distance kernel keeps
     const int64_t n_q = img_offsets[n_images];
     const int64_t rb = row_bytes(dtype);
     const int64_t nc = ix->n_classes;
@@ -669,7 +683,7 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
     if ((rc = ensure_ws(ix, ix->ws, std::max<int64_t>(1, n_q), n_images, part,
                         (want_nbr && !dev) ? n_q * kp : 0, dev ? 0 : n_q * rb, fp8)))
         return rc;
-    if (fp8 && (rc = ensure_fp8_ws(ix, ix->ws, q_max, list_len, k))) return rc;
+    if (fp8 && (rc = ensure_fp8_ws(ix, ix->ws, q_max, fp8_candidates(k), k))) return rc;
     Workspace &ws = ix->ws;
 
     // the shared workspace may still be read by a call on another stream
@@ -707,6 +721,7 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
         io.totals = ws.totals;
         io.nbr_idx = d_nbr_i;
         io.nbr_dist = d_nbr_d;
+        io.ws = &ws;
         io.part_d = ws.part_d;
         io.part_i = ws.part_i;
         io.totals_f64 = ws.totals_f64;
@@ -778,7 +793,7 @@ extern "C" int lnbnn_set_tuning(lnbnn_index *ix, int mode, int32_t k, const lnbn
     if (t->chunk_tiles < 0 || t->chunk_tiles % 8 != 0) return set_err(LNBNN_EINVAL, "chunk_tiles must be a multiple of 8");
     if (t->max_workgroups < 0) return set_err(LNBNN_EINVAL, "negative max_workgroups");
     const int fmt = mode_fmt(mode);
-    const int list_len = mode == LNBNN_FP8_RERANK ? fp8_candidates(k) : k + 1;
+    const int list_len = dist_list_len(mode, k);
     const int kpb = kp_bucket(list_len, fmt);
     if (kpb == 0) return set_err(LNBNN_EINVAL, "k = %d is not supported by mode %d", k, mode);
     if (t->variant >= 0 && !variant_supports(t->variant, fmt, list_len))
@@ -841,7 +856,7 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
     if (rc) return rc;
     if (mode == LNBNN_EXACT_I8) return set_err(LNBNN_EINVAL, "mode %d is not built in this library", mode);
     const int fmt = mode_fmt(mode);
-    const int kpb = kp_bucket(mode == LNBNN_FP8_RERANK ? fp8_candidates(k) : k + 1, fmt);
+    const int kpb = kp_bucket(dist_list_len(mode, k), fmt);
     char arch[64] = "gfx";
     {
         hipDeviceProp_t prop;
@@ -852,7 +867,7 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
     if (cache_path) {
         auto m = read_cache(cache_path);
         auto it = m.find(key.str());
-        if (it != m.end() && variant_supports(it->second, fmt, mode == LNBNN_FP8_RERANK ? fp8_candidates(k) : k + 1)) {
+        if (it != m.end() && variant_supports(it->second, fmt, dist_list_len(mode, k))) {
             std::lock_guard<std::mutex> lock(ix->plan_mu);
             ix->pinned[{mode, kpb}] = lnbnn_tuning{it->second, 0, 0};
             if (best_variant) *best_variant = it->second;
@@ -865,7 +880,7 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
     LN_HIP(hipMalloc((void **)&d_cls, std::max<int32_t>(1, n_images) * 4));
     int best = -1;
     double best_ms = 1e30;
-    const int list_len = mode == LNBNN_FP8_RERANK ? fp8_candidates(k) : k + 1;
+    const int list_len = dist_list_len(mode, k);
     for (int v = 0; v < num_variants(); ++v) {
         if (!variant_supports(v, fmt, list_len)) continue;
         if ((rc = lnbnn_set_variant(ix, mode, k, v))) break;

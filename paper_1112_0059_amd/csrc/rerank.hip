@@ -3,7 +3,7 @@
 //   k_fp8_rowprep   per reference: power-of-two scale, E8M0 exponent, seed
 //   k_fp8_pack      references -> FP8 A-fragment tiles
 //   k_fp8_qprep     queries -> FP8 codes of -q * 2^e_q and E8M0 2^(1-e_q)
-//   k_cand_merge    per query: 4k best candidates over the slice lists
+//   k_cand_merge    per query: 4k best candidates over the half/slice lists
 //   k_rerank        per query (one wave): exact FP32 squared distances of the
 //                   candidates, the k+1 nearest by (distance, index), and
 //                   Algorithm 2's per-class updates dist_C - dist_B
@@ -131,7 +131,8 @@ static __device__ __forceinline__ bool pair_less(float d0, int i0, float d1, int
 }
 
 // One thread per query: the n_cand best (key, index) pairs over the
-// 2 * n_slices sorted candidate lists.
+// 2 * n_slices sorted candidate lists of kp_stride entries each (together at
+// least n_cand; entries past a list's real rows carry +inf keys and lose).
 __global__ __launch_bounds__(256) void k_cand_merge(RerankArgs a)
 {
     const int64_t n_q = a.bd->n_q;
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(256) void k_cand_merge(RerankArgs a)
             float bd = __builtin_inff();
             int bi = -1, bl = 0;
             for (int l = 0; l < a.n_lists; ++l) {
-                if (heads[l] >= a.n_cand) continue;
+                if (heads[l] >= a.kp_stride) continue;
                 const int64_t o = ((int64_t)l * a.q_cap + q) * a.kp_stride + heads[l];
                 const float d = a.part_d[o];
                 const int i = a.part_i[o];

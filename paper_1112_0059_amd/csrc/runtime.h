@@ -73,6 +73,7 @@ struct Plan {
 
 // Everything a batch launch sequence needs; pointers are device pointers.
 struct BatchIO {
+    const Workspace *ws = nullptr;      // owner of the buffers below (capacity checks)
     const void *q = nullptr;
     const int64_t *offsets = nullptr;
     const BatchDesc *bd = nullptr;
@@ -150,6 +151,7 @@ int ensure_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int64_t img_cap, in
               int64_t nbr, int64_t qbytes, bool need_f64);
 int ensure_fp8_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int n_cand, int k);
 int fp8_candidates(int k);
+int dist_list_len(int mode, int k);
 int64_t row_bytes(int dtype);
 
 int launch_graph(std::map<std::string, GraphEntry> &graphs, lnbnn_index *ix, const Plan &p, const BatchIO &io,

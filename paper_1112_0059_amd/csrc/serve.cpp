@@ -94,12 +94,12 @@ static int64_t slot_bytes(lnbnn_index *ix, int64_t cap, int64_t img_cap)
     const bool fp8 = ix->dtype == LNBNN_F32;
     // worst case over the k a request may ask for: the longest lists
     const int kmax = fp8 ? kMaxFp8K : LNBNN_MAX_K;
-    const int list = fp8 ? fp8_candidates(kmax) : kmax + 1;
+    const int list = kp_bucket(dist_list_len(fp8 ? LNBNN_FP8_RERANK : 0, kmax), fp8 ? FMT_FP8 : FMT_F16);
     const int64_t slices = 32;   // upper bound of the plan's split
     int64_t b = cap * row_bytes_for_mode(fp8 ? LNBNN_FP8_RERANK : 0);
     b += slices * 2 * cap * (int64_t)list * 8;
     b += img_cap * (16 + 8 + ix->n_classes * 16 + 4) + 16;
-    if (fp8) b += cap * (kDim + 4) + cap * list * 4 + cap * kmax * 12;
+    if (fp8) b += cap * (kDim + 4) + cap * (int64_t)fp8_candidates(kmax) * 4 + cap * kmax * 12;
     return b;
 }
 
@@ -112,13 +112,12 @@ static int setup_slot(Server *sv, Slot *sl)
     LN_HIP(hipEventCreateWithFlags(&sl->done, hipEventDisableTiming));
     sl->ws.device = ix->device;
     const int kmax = fp8 ? kMaxFp8K : LNBNN_MAX_K;
-    const int list = fp8 ? fp8_candidates(kmax) : kmax + 1;
     // partial lists: the largest layout any (mode, k, batch bucket) plans
     int64_t part = 0;
     for (int mode = 0; mode < 3; ++mode) {
         if (!(ix->modes & LNBNN_MODE_BIT(mode))) continue;
         for (int k = 1; k <= kmax; ++k) {
-            const int len = mode == LNBNN_FP8_RERANK ? fp8_candidates(k) : k + 1;
+            const int len = dist_list_len(mode, k);
             for (int64_t q = 1024; ; q = std::min(cap, q * 2)) {
                 Plan p;
                 if (make_plan(ix, mode, len, std::min(q, cap), -1, &p) == LNBNN_OK)
@@ -130,7 +129,7 @@ static int setup_slot(Server *sv, Slot *sl)
     const int64_t rb = row_bytes_for_mode(fp8 ? LNBNN_FP8_RERANK : 0);
     int rc = ensure_ws(ix, sl->ws, cap, img, part, 0, cap * rb, fp8);
     if (rc) return rc;
-    if (fp8 && (rc = ensure_fp8_ws(ix, sl->ws, cap, list, kmax))) return rc;
+    if (fp8 && (rc = ensure_fp8_ws(ix, sl->ws, cap, fp8_candidates(kmax), kmax))) return rc;
     LN_HIP(hipHostMalloc((void **)&sl->h_q, std::max<int64_t>(1, cap * rb), hipHostMallocDefault));
     LN_HIP(hipHostMalloc((void **)&sl->h_off, (img + 1) * 8, hipHostMallocDefault));
     LN_HIP(hipHostMalloc((void **)&sl->h_bd, sizeof(BatchDesc), hipHostMallocDefault));
@@ -180,7 +179,7 @@ static int launch_slot(Server *sv, Slot *sl)
     while (bucket < n_q) bucket *= 2;
     bucket = std::min(bucket, sv->max_batch_desc);
     Plan plan;
-    int rc = make_plan(ix, mode, fp8 ? fp8_candidates(k) : k + 1, std::max<int64_t>(1, bucket), -1, &plan);
+    int rc = make_plan(ix, mode, dist_list_len(mode, k), std::max<int64_t>(1, bucket), -1, &plan);
     if (rc) return rc;
     BatchIO io;
     io.q = ws.q;
@@ -193,6 +192,7 @@ static int launch_slot(Server *sv, Slot *sl)
     io.cls = ws.cls;
     io.totals = ws.totals;
     io.totals_f64 = ws.totals_f64;
+    io.ws = &ws;
     io.part_d = ws.part_d;
     io.part_i = ws.part_i;
     io.q8 = ws.q8;
