@@ -62,7 +62,8 @@ enum {
     LNBNN_FP8_RERANK = 2,  /* f32 data: FP8 e4m3 candidate pass, exact FP32 re-rank of 4k
                               candidates (the best 4k FP8 keys of the union of per-row-half
                               lists of >= 2k keys each; the FP8 top 2k are always among them) */
-    LNBNN_EXACT_I8 = 3     /* u8 data shifted by -128, INT8 matrix cores, INT32 accumulate: exact */
+    LNBNN_EXACT_I8 = 3     /* u8 data shifted by -128, INT8 matrix cores, INT32 accumulate: exact
+                              (the fastest exact mode; results identical to FP16/BF16) */
 };
 #define LNBNN_MODE_BIT(m) (1u << (m))
 

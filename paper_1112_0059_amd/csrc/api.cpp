@@ -266,6 +266,7 @@ int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t
     // never read by the unscaled formats; any valid address keeps the
     // kernel's pointer arithmetic defined
     a.row_scale = ix->row_scale ? ix->row_scale : reinterpret_cast<const int32_t *>(a.seed);
+    a.parity = ix->parity ? ix->parity : reinterpret_cast<const uint32_t *>(a.seed);
     a.n_tiles = ix->n_pad / kTileRows;
     a.tiles_per_slice = p.tiles_per_slice;
     a.n_slices = p.n_slices;
@@ -303,6 +304,7 @@ int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t
     } else {
         FinishArgs f{};
         f.q = io.q;
+        f.q_shift = p.fmt == FMT_I8 ? 128 : 0;
         f.bd = io.bd;
         f.offsets = io.offsets;
         f.labels = ix->labels;
@@ -339,7 +341,10 @@ static int free_index_buffers(lnbnn_index *ix)
     if (ix->seed[FMT_F16]) (void)hipFree(ix->seed[FMT_F16]);
     else if (ix->seed[FMT_BF16]) (void)hipFree(ix->seed[FMT_BF16]);
     if (ix->seed[FMT_FP8]) (void)hipFree(ix->seed[FMT_FP8]);
+    if (ix->seed[FMT_I8]) (void)hipFree(ix->seed[FMT_I8]);
     for (int f = 0; f < 4; ++f) ix->seed[f] = nullptr;
+    if (ix->parity) (void)hipFree(ix->parity);
+    ix->parity = nullptr;
     if (ix->labels) (void)hipFree(ix->labels);
     if (ix->ref_f32) (void)hipFree(ix->ref_f32);
     if (ix->row_scale) (void)hipFree(ix->row_scale);
@@ -361,11 +366,11 @@ extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, in
     if (n_classes < 1) return set_err(LNBNN_EINVAL, "n_classes must be >= 1");
     if (dtype != LNBNN_U8 && dtype != LNBNN_F32) return set_err(LNBNN_EINVAL, "bad dtype %d", dtype);
     if (hbm_budget_bytes < 0) return set_err(LNBNN_EINVAL, "negative HBM budget");
-    const uint32_t exact = LNBNN_MODE_BIT(LNBNN_EXACT_F16) | LNBNN_MODE_BIT(LNBNN_EXACT_BF16);
+    const uint32_t exact = LNBNN_MODE_BIT(LNBNN_EXACT_F16) | LNBNN_MODE_BIT(LNBNN_EXACT_BF16) |
+                           LNBNN_MODE_BIT(LNBNN_EXACT_I8);
     if (mode_mask == 0) return set_err(LNBNN_EINVAL, "empty mode mask");
     if (dtype == LNBNN_U8 && (mode_mask & ~exact))
-        return set_err(LNBNN_EINVAL, "mode mask 0x%x: u8 data builds only the exact FP16/BF16 modes",
-                       mode_mask);
+        return set_err(LNBNN_EINVAL, "mode mask 0x%x: u8 data builds only the exact modes", mode_mask);
     if (dtype == LNBNN_F32 && mode_mask != LNBNN_MODE_BIT(LNBNN_FP8_RERANK))
         return set_err(LNBNN_EINVAL, "mode mask 0x%x: float data builds only the FP8 re-rank mode", mode_mask);
     if (flags & ~(uint32_t)LNBNN_DEVICE_PTRS) return set_err(LNBNN_EINVAL, "unknown flags 0x%x", flags);
@@ -469,6 +474,20 @@ extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, in
         seeded = true;
         ix->seed[fmt] = seed;
     }
+    if (!rc && dtype == LNBNN_U8 && (mode_mask & LNBNN_MODE_BIT(LNBNN_EXACT_I8))) {
+        // INT8 mode: its own fragments, seeds and parity masks
+        int32_t *iseed = nullptr;
+        rc = grow((void **)&ix->frag[FMT_I8], 0, ix->n_pad * kDim, 1);
+        if (!rc) rc = grow((void **)&iseed, 0, ix->n_pad, 4);
+        if (!rc) ix->seed[FMT_I8] = reinterpret_cast<float *>(iseed);
+        if (!rc) rc = grow((void **)&ix->parity, 0, ix->n_pad / kTileRows, 4);
+        if (!rc) {
+            bytes += ix->n_pad * (kDim + 4) + ix->n_pad / kTileRows * 4;
+            hipError_t e = launch_pack_i8(static_cast<const uint8_t *>(d_refs), n_refs, ix->n_pad, ix->frag[FMT_I8],
+                                          iseed, ix->parity, s);
+            if (e != hipSuccess) rc = hip_err(e, "pack i8");
+        }
+    }
     hipError_t e = hipStreamSynchronize(s);
     if (staged) (void)hipFree(staged);
     if (rc) {
@@ -476,6 +495,10 @@ extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, in
         return fail(rc);
     }
     if (e != hipSuccess) return fail(hip_err(e, "build_index sync"));
+    if (seed && !seeded) {   // no mode used the shared seed buffer
+        (void)hipFree(seed);
+        bytes -= ix->n_pad * 4;
+    }
     ix->device_bytes = bytes;
     size_t free_b = 0, total_b = 0;
     LN_HIP(hipMemGetInfo(&free_b, &total_b));
@@ -650,7 +673,6 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
                                out_nbr_idx, out_nbr_dist);
     if (rc) return rc;
     if (n_images == 0) return LNBNN_OK;
-    if (mode == LNBNN_EXACT_I8) return set_err(LNBNN_EINVAL, "mode %d is not built in this library", mode);
     std::lock_guard<std::mutex> lock(ix->mu);
     LN_HIP(hipSetDevice(ix->device));
     hipStream_t s = stream ? (hipStream_t)stream : ix->own_stream;
@@ -854,7 +876,6 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
     int rc = validate_classify(ix, queries_dev, dtype, img_offsets, n_images, k, mode, LNBNN_DEVICE_PTRS, true,
                                nullptr, nullptr);
     if (rc) return rc;
-    if (mode == LNBNN_EXACT_I8) return set_err(LNBNN_EINVAL, "mode %d is not built in this library", mode);
     const int fmt = mode_fmt(mode);
     const int kpb = kp_bucket(dist_list_len(mode, k), fmt);
     char arch[64] = "gfx";

@@ -17,6 +17,8 @@
 namespace lnbnn {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x4v __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
@@ -44,7 +46,40 @@ static __device__ __forceinline__ uint32_t byte_at(uint2 r, int e)
 // accumulator seeded with ||r~||^2 yields ||r~||^2 - 2 q~.r~ of the
 // dequantised values.
 // ---------------------------------------------------------------------------
-struct OpF16 {
+static __device__ __forceinline__ float min16(const f32x16 &acc)
+{
+    const float m0 = __builtin_fminf(__builtin_fminf(acc[0], acc[1]), acc[2]);
+    const float m1 = __builtin_fminf(__builtin_fminf(acc[3], acc[4]), acc[5]);
+    const float m2 = __builtin_fminf(__builtin_fminf(acc[6], acc[7]), acc[8]);
+    const float m3 = __builtin_fminf(__builtin_fminf(acc[9], acc[10]), acc[11]);
+    const float m4 = __builtin_fminf(__builtin_fminf(acc[12], acc[13]), acc[14]);
+    float mn = __builtin_fminf(__builtin_fminf(m0, m1), __builtin_fminf(m2, m3));
+    return __builtin_fminf(__builtin_fminf(mn, m4), acc[15]);
+}
+
+static __device__ __forceinline__ int min16(const i32x16 &a)
+{
+    const int m0 = min(min(a[0], a[1]), a[2]);
+    const int m1 = min(min(a[3], a[4]), a[5]);
+    const int m2 = min(min(a[6], a[7]), a[8]);
+    const int m3 = min(min(a[9], a[10]), a[11]);
+    const int m4 = min(min(a[12], a[13]), a[14]);
+    const int mn = min(min(m0, m1), min(m2, m3));
+    return min(min(mn, m4), a[15]);
+}
+
+// Float formats: the accumulator is the ranking key d' itself.  The gate
+// compares a tile's smallest key with the list's KP-th key.
+struct FloatKeys {
+    using acc_t = f32x16;
+    static constexpr bool kParity = false;
+    static __device__ __forceinline__ float init() { return __builtin_inff(); }
+    static __device__ __forceinline__ float gate_min(const f32x16 &acc) { return min16(acc); }
+    static __device__ __forceinline__ float gate_thr(float thr) { return thr; }
+    static __device__ __forceinline__ float key(const f32x16 &acc, int r, uint32_t, int) { return acc[r]; }
+};
+
+struct OpF16 : FloatKeys {
     static constexpr int kFmt = FMT_F16;
     static constexpr int kSteps = 8;
     static constexpr int kAU = 1;          // uint4 per lane per step
@@ -68,6 +103,13 @@ struct OpF16 {
         }
         sb = 127;
     }
+    // A fragment of K step s for one reference row (zeros past the end)
+    static __device__ __forceinline__ uint4 pack_frag(const uint8_t *row, bool ok, int s, int h)
+    {
+        uint2 raw = make_uint2(0u, 0u);
+        if (ok) raw = *reinterpret_cast<const uint2 *>(row + 16 * s + 8 * h);
+        return cvt8(raw, 1.0f);
+    }
     static __device__ __forceinline__ f32x16 mma(const uint4 (&a)[kAU], const uint4 (&b)[kAU], f32x16 c, int, int)
     {
         return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a[0]),
@@ -75,7 +117,7 @@ struct OpF16 {
     }
 };
 
-struct OpBF16 {
+struct OpBF16 : FloatKeys {
     static constexpr int kFmt = FMT_BF16;
     static constexpr int kSteps = 8;
     static constexpr int kAU = 1;
@@ -99,6 +141,13 @@ struct OpBF16 {
         }
         sb = 127;
     }
+    // A fragment of K step s for one reference row (zeros past the end)
+    static __device__ __forceinline__ uint4 pack_frag(const uint8_t *row, bool ok, int s, int h)
+    {
+        uint2 raw = make_uint2(0u, 0u);
+        if (ok) raw = *reinterpret_cast<const uint2 *>(row + 16 * s + 8 * h);
+        return cvt8(raw, 1.0f);
+    }
     static __device__ __forceinline__ f32x16 mma(const uint4 (&a)[kAU], const uint4 (&b)[kAU], f32x16 c, int, int)
     {
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[0]),
@@ -106,7 +155,7 @@ struct OpBF16 {
     }
 };
 
-struct OpFP8 {
+struct OpFP8 : FloatKeys {
     static constexpr int kFmt = FMT_FP8;
     static constexpr int kSteps = 2;
     static constexpr int kAU = 2;
@@ -131,6 +180,66 @@ struct OpFP8 {
         bv[0] = (int)b[0].x; bv[1] = (int)b[0].y; bv[2] = (int)b[0].z; bv[3] = (int)b[0].w;
         bv[4] = (int)b[1].x; bv[5] = (int)b[1].y; bv[6] = (int)b[1].z; bv[7] = (int)b[1].w;
         return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, c, 0, 0, 0, sa, 0, sb);
+    }
+};
+
+// INT8 (v_mfma_i32_32x32x32_i8, INT32 accumulation: exact).  With s = r - 128
+// and t = q - 128 (both int8), ||q - r||^2 = ||t - s||^2 = ||t||^2 + key with
+//     key = ||s||^2 - 2 t.s,
+// a per-query shift of the squared distance.  The factor 2 does not fit an
+// int8 operand, so the accumulator carries
+//     D = floor(||s||^2 / 2) - t.s,   key = 2 D + b,   b = ||s||^2 mod 2,
+// from the seed floor(||s||^2 / 2) + sum(s) and the query operand
+// u = 127 - q = -t - 1 (so u.s = -t.s - sum(s)).  |D| < 2^22, so every
+// key is an exact FP32 integer.  The per-row bit b lives in a per-tile
+// mask that only the (rare) insertion path reads.  A K step covers 32
+// elements: lane l supplies 16 bytes of row (l & 31), K elements
+// 32*s + 16*(l >> 5) + e.  Padding rows carry the seed 2^30, whose D never
+// makes a key (see key()).
+struct OpI8 {
+    static constexpr int kFmt = FMT_I8;
+    static constexpr int kSteps = 4;
+    static constexpr int kAU = 1;
+    static constexpr bool kScaled = false;
+    using acc_t = i32x16;
+    static constexpr bool kParity = true;
+    static constexpr int kPadSeed = 1 << 30;
+    static __device__ __forceinline__ int init() { return 0x7fffffff; }
+    static __device__ __forceinline__ float gate_min(const i32x16 &acc) { return (float)min16(acc); }
+    // key = 2D + b < thr implies D < ceil(thr / 2)
+    static __device__ __forceinline__ float gate_thr(float thr) { return __builtin_ceilf(0.5f * thr); }
+    static __device__ __forceinline__ float key(const i32x16 &acc, int r, uint32_t parity, int h)
+    {
+        const int d = acc[r];
+        const int row = 8 * (r >> 2) + 4 * h + (r & 3);
+        return d >= (1 << 29) ? __builtin_inff() : (float)(2 * d + (int)((parity >> row) & 1u));
+    }
+    static __device__ __forceinline__ void load_b(const void *q, const int32_t *, int64_t qi, bool ok, int h,
+                                                  uint4 (&b)[kSteps][kAU], int &sb)
+    {
+        const uint4 *qrow = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(q) + (ok ? qi : 0) * kDim);
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s) {
+            // bytes 127 - q: q ^ 0x7f reads as that int8 for every q in 0..255
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (ok) v = qrow[2 * s + h];
+            const uint32_t m = 0x7f7f7f7fu;
+            b[s][0] = ok ? make_uint4(v.x ^ m, v.y ^ m, v.z ^ m, v.w ^ m) : make_uint4(0u, 0u, 0u, 0u);
+        }
+        sb = 127;
+    }
+    static __device__ __forceinline__ uint4 pack_frag(const uint8_t *row, bool ok, int s, int h)
+    {
+        // bytes r ^ 0x80 read as the int8 r - 128
+        if (!ok) return make_uint4(0u, 0u, 0u, 0u);
+        const uint4 v = *reinterpret_cast<const uint4 *>(row + 32 * s + 16 * h);
+        const uint32_t m = 0x80808080u;
+        return make_uint4(v.x ^ m, v.y ^ m, v.z ^ m, v.w ^ m);
+    }
+    static __device__ __forceinline__ i32x16 mma(const uint4 (&a)[kAU], const uint4 (&b)[kAU], i32x16 c, int, int)
+    {
+        return __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(i32x4v, a[0]), __builtin_bit_cast(i32x4v, b[0]),
+                                                     c, 0, 0, 0);
     }
 };
 
@@ -171,48 +280,49 @@ static __device__ __forceinline__ void list_insert(float v, int idx, float (&ld)
     thr = ld[KP - 1];
 }
 
-static __device__ __forceinline__ float min16(const f32x16 &acc)
+// Load through the scalar cache (uniform index).
+static __device__ __forceinline__ uint32_t load_uniform(const uint32_t *p, int i)
 {
-    const float m0 = __builtin_fminf(__builtin_fminf(acc[0], acc[1]), acc[2]);
-    const float m1 = __builtin_fminf(__builtin_fminf(acc[3], acc[4]), acc[5]);
-    const float m2 = __builtin_fminf(__builtin_fminf(acc[6], acc[7]), acc[8]);
-    const float m3 = __builtin_fminf(__builtin_fminf(acc[9], acc[10]), acc[11]);
-    const float m4 = __builtin_fminf(__builtin_fminf(acc[12], acc[13]), acc[14]);
-    float mn = __builtin_fminf(__builtin_fminf(m0, m1), __builtin_fminf(m2, m3));
-    return __builtin_fminf(__builtin_fminf(mn, m4), acc[15]);
+    return ((const __attribute__((address_space(4))) uint32_t *)p)[i];
 }
 
-// Insert every value of one tile that beats the list's current KP-th value.
-template <int KP>
-static __device__ __forceinline__ void tile_insert(const f32x16 &acc, float &thr, float (&ld)[KP], int (&li)[KP],
-                                                   int row0)
+// Insert every key of one tile that beats the list's current KP-th key;
+// gt is the gate threshold that goes with the list's new KP-th key.
+template <class Op, int KP>
+static __device__ __forceinline__ void tile_insert(const typename Op::acc_t &acc, float &thr, float &gt,
+                                                   float (&ld)[KP], int (&li)[KP], int row0, int h,
+                                                   const uint32_t *parity)
 {
+    uint32_t pm = 0;
+    if constexpr (Op::kParity) pm = load_uniform(parity, __builtin_amdgcn_readfirstlane(row0 >> 5));
     // the row base is made opaque here so the 16 index computations stay on
     // this (rarely taken) path instead of being hoisted into the gate
     int base = row0;
     asm volatile("" : "+v"(base));
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        const float v = acc[r];
+        const float v = Op::key(acc, r, pm, h);
         const bool take = v < thr;
         if (__builtin_amdgcn_ballot_w64(take) != 0) {
             if (take) list_insert<KP>(v, base + 8 * (r >> 2) + (r & 3), ld, li, thr);
         }
     }
+    gt = Op::gate_thr(thr);
 }
 
 // Gate + insert for the NT query tiles of one reference tile.  All gates
 // are computed before any branch so they can overlap the next MFMA chain.
-template <int KP, int NT>
-static __device__ __forceinline__ void tiles_select(const f32x16 (&acc)[NT], float (&thr)[NT], float (&ld)[NT][KP],
-                                                    int (&li)[NT][KP], int row0)
+template <class Op, int KP, int NT>
+static __device__ __forceinline__ void tiles_select(const typename Op::acc_t (&acc)[NT], float (&thr)[NT],
+                                                    float (&gt)[NT], float (&ld)[NT][KP], int (&li)[NT][KP],
+                                                    int row0, int h, const uint32_t *parity)
 {
     bool any[NT];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) any[nt] = __builtin_amdgcn_ballot_w64(min16(acc[nt]) < thr[nt]) != 0;
+    for (int nt = 0; nt < NT; ++nt) any[nt] = __builtin_amdgcn_ballot_w64(Op::gate_min(acc[nt]) < gt[nt]) != 0;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
-        if (any[nt]) tile_insert<KP>(acc[nt], thr[nt], ld[nt], li[nt], row0);
+        if (any[nt]) tile_insert<Op, KP>(acc[nt], thr[nt], gt[nt], ld[nt], li[nt], row0, h, parity);
 }
 
 typedef __attribute__((address_space(1))) const void *gmem_ptr;
@@ -263,44 +373,132 @@ static __device__ __forceinline__ void wait_vmcnt()
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+static __device__ __forceinline__ uint32_t lds_addr(const void *p)
+{
+    return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const void *)p;
+}
+
+// All LDS reads of one tile (A fragments, seeds, row scales) as one block
+// that also waits for them.  The compiler cannot tell which of the stage
+// buffers an asynchronous global-to-LDS copy is still filling, so reads it
+// emits itself would wait for every copy in flight, including the prefetch
+// of later stages; the stage loop's own vmcnt wait and barrier already
+// order each read after the copy it needs.
+template <class Op>
+static __device__ __forceinline__ void tile_reads(const uint4 *frag, const float4 *seed, const int32_t *rsc,
+                                                  int lane, int h, uint4 (&av)[Op::kSteps][Op::kAU], f32x16 &sd,
+                                                  int &sa)
+{
+    const uint32_t fa = lds_addr(frag + lane);
+    const uint32_t ea = lds_addr(seed + h);
+    u32x4 a0, a1, a2, a3, a4, a5, a6, a7;
+    f32x4 s0, s1, s2, s3;
+    if constexpr (Op::kSteps * Op::kAU == 8) {
+        static_assert(!Op::kScaled, "unscaled formats only");
+        asm volatile(
+            "ds_read_b128 %0, %12\n\t"
+            "ds_read_b128 %1, %12 offset:1024\n\t"
+            "ds_read_b128 %2, %12 offset:2048\n\t"
+            "ds_read_b128 %3, %12 offset:3072\n\t"
+            "ds_read_b128 %4, %12 offset:4096\n\t"
+            "ds_read_b128 %5, %12 offset:5120\n\t"
+            "ds_read_b128 %6, %12 offset:6144\n\t"
+            "ds_read_b128 %7, %12 offset:7168\n\t"
+            "ds_read_b128 %8, %13\n\t"
+            "ds_read_b128 %9, %13 offset:32\n\t"
+            "ds_read_b128 %10, %13 offset:64\n\t"
+            "ds_read_b128 %11, %13 offset:96\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(a0), "=&v"(a1), "=&v"(a2), "=&v"(a3), "=&v"(a4), "=&v"(a5), "=&v"(a6), "=&v"(a7),
+              "=&v"(s0), "=&v"(s1), "=&v"(s2), "=&v"(s3)
+            : "v"(fa), "v"(ea)
+            : "memory");
+        const u32x4 a[8] = {a0, a1, a2, a3, a4, a5, a6, a7};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) av[s][0] = __builtin_bit_cast(uint4, a[s]);
+        sa = 127;
+    } else if constexpr (!Op::kScaled) {
+        static_assert(Op::kSteps * Op::kAU == 4, "INT8 layout");
+        asm volatile(
+            "ds_read_b128 %0, %8\n\t"
+            "ds_read_b128 %1, %8 offset:1024\n\t"
+            "ds_read_b128 %2, %8 offset:2048\n\t"
+            "ds_read_b128 %3, %8 offset:3072\n\t"
+            "ds_read_b128 %4, %9\n\t"
+            "ds_read_b128 %5, %9 offset:32\n\t"
+            "ds_read_b128 %6, %9 offset:64\n\t"
+            "ds_read_b128 %7, %9 offset:96\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(a0), "=&v"(a1), "=&v"(a2), "=&v"(a3), "=&v"(s0), "=&v"(s1), "=&v"(s2), "=&v"(s3)
+            : "v"(fa), "v"(ea)
+            : "memory");
+        const u32x4 a[4] = {a0, a1, a2, a3};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) av[s][0] = __builtin_bit_cast(uint4, a[s]);
+        sa = 127;
+    } else {
+        static_assert(Op::kSteps * Op::kAU == 4 && Op::kScaled, "FP8 layout");
+        const uint32_t ra = lds_addr(rsc + (lane & 31));
+        int r;
+        asm volatile(
+            "ds_read_b128 %0, %9\n\t"
+            "ds_read_b128 %1, %9 offset:1024\n\t"
+            "ds_read_b128 %2, %9 offset:2048\n\t"
+            "ds_read_b128 %3, %9 offset:3072\n\t"
+            "ds_read_b128 %4, %10\n\t"
+            "ds_read_b128 %5, %10 offset:32\n\t"
+            "ds_read_b128 %6, %10 offset:64\n\t"
+            "ds_read_b128 %7, %10 offset:96\n\t"
+            "ds_read_b32 %8, %11\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(a0), "=&v"(a1), "=&v"(a2), "=&v"(a3), "=&v"(s0), "=&v"(s1), "=&v"(s2), "=&v"(s3), "=&v"(r)
+            : "v"(fa), "v"(ea), "v"(ra)
+            : "memory");
+        av[0][0] = __builtin_bit_cast(uint4, a0);
+        av[0][1] = __builtin_bit_cast(uint4, a1);
+        av[1][0] = __builtin_bit_cast(uint4, a2);
+        av[1][1] = __builtin_bit_cast(uint4, a3);
+        sa = r;
+    }
+    const f32x4 sv[4] = {s0, s1, s2, s3};
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sd[4 * g + j] = sv[g][j];
+}
+
 // One pipeline step: the MFMA chain of a new tile (into acc_new) and the
 // gate of the previous tile (acc_old), scheduled as one block: all LDS reads
 // of the new tile first, then MFMAs interleaved with the gate's vector ops.
 // Insertions for the previous tile (rare) follow after the block.
 template <class Op, int KP, int NT>
-static __device__ __forceinline__ void pipe_step(f32x16 (&acc_new)[NT], const f32x16 (&acc_old)[NT],
+static __device__ __forceinline__ void pipe_step(typename Op::acc_t (&acc_new)[NT],
+                                                 const typename Op::acc_t (&acc_old)[NT],
                                                  const uint4 (&bq)[NT][Op::kSteps][Op::kAU], const int (&sb)[NT],
                                                  const uint4 *frag, const float4 *seed, const int32_t *rsc, int lane,
-                                                 int h, float (&thr)[NT], float (&ld)[NT][KP], int (&li)[NT][KP],
-                                                 int row_old)
+                                                 int h, float (&thr)[NT], float (&gt)[NT], float (&ld)[NT][KP],
+                                                 int (&li)[NT][KP], int row_old, const uint32_t *parity)
 {
+    using acc_t = typename Op::acc_t;
     constexpr int S = Op::kSteps;
     constexpr int AU = Op::kAU;
     f32x16 sd;
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        const float4 sv = seed[2 * g + h];
-        sd[4 * g + 0] = sv.x;
-        sd[4 * g + 1] = sv.y;
-        sd[4 * g + 2] = sv.z;
-        sd[4 * g + 3] = sv.w;
-    }
-    int sa = 127;
-    if constexpr (Op::kScaled) sa = rsc[lane & 31];
+    int sa;
     uint4 av[S][AU];
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-#pragma unroll
-        for (int u = 0; u < AU; ++u) av[s][u] = frag[(s * AU + u) * 64 + lane];
+    tile_reads<Op>(frag, seed, rsc, lane, h, av, sd, sa);
+    const acc_t seed_acc = __builtin_bit_cast(acc_t, sd);
     bool any[NT];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) any[nt] = __builtin_amdgcn_ballot_w64(min16(acc_old[nt]) < thr[nt]) != 0;
+    for (int nt = 0; nt < NT; ++nt) any[nt] = __builtin_amdgcn_ballot_w64(Op::gate_min(acc_old[nt]) < gt[nt]) != 0;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc_new[nt] = Op::mma(av[s], bq[nt][s], s == 0 ? sd : acc_new[nt], sa, sb[nt]);
+        for (int nt = 0; nt < NT; ++nt)
+            acc_new[nt] = Op::mma(av[s], bq[nt][s], s == 0 ? seed_acc : acc_new[nt], sa, sb[nt]);
     }
-    __builtin_amdgcn_sched_group_barrier(0x100, S * AU + 4 + (Op::kScaled ? 1 : 0), 0);   // LDS reads
 #pragma unroll
     for (int i = 0; i < S * NT; ++i) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);     // one MFMA
@@ -308,7 +506,7 @@ static __device__ __forceinline__ void pipe_step(f32x16 (&acc_new)[NT], const f3
     }
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
-        if (any[nt]) tile_insert<KP>(acc_old[nt], thr[nt], ld[nt], li[nt], row_old);
+        if (any[nt]) tile_insert<Op, KP>(acc_old[nt], thr[nt], gt[nt], ld[nt], li[nt], row_old, h, parity);
 }
 
 template <class Op, int KP, int NT, int MT, int W, int NB>
@@ -367,7 +565,7 @@ void k_dist_topk(DistArgs a)
 
             float ld[NT][KP];
             int li[NT][KP];
-            float thr[NT];
+            float thr[NT], gt[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int64_t base = ((int64_t)(slice * 2 + h) * a.q_cap + qi[nt]) * KP;
@@ -378,6 +576,7 @@ void k_dist_topk(DistArgs a)
                     li[nt][p] = load ? a.part_i[base + p] : -1;
                 }
                 thr[nt] = ld[nt][KP - 1];
+                gt[nt] = Op::gate_thr(thr[nt]);
             }
 
             // Prologue: stages 0..PD-1 in flight, wait for stage 0.  Stages
@@ -398,12 +597,12 @@ void k_dist_topk(DistArgs a)
             // Software pipeline over pairs of tiles: the MFMA chain of one
             // tile is issued in the same block as the gate of the previous
             // tile, so the matrix cores keep working while the gate's vector
-            // ops run.  The "previous tile" of the first step is all +inf.
-            f32x16 acc0[NT], acc1[NT];
+            // ops run.  The "previous tile" of the first step holds no key.
+            typename Op::acc_t acc0[NT], acc1[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) acc1[nt][r] = __builtin_inff();
+                for (int r = 0; r < 16; ++r) acc1[nt][r] = Op::init();
             int row_prev = 0;
             int buf = 0;
             for (int st = 0; st < n_st; ++st) {
@@ -419,21 +618,27 @@ void k_dist_topk(DistArgs a)
                 for (int m = 0; m < MT; m += 2) {
                     const int row_t = (int)((t0 + (int64_t)st * MT + m) * kTileRows) + 4 * h;
                     pipe_step<Op, KP, NT>(acc0, acc1, bq, sb, s_frag[buf] + m * TILE_U4, s_seed[buf] + m * 8,
-                                          s_rsc[buf] + (Op::kScaled ? m * kTileRows : 0), lane, h, thr, ld, li,
-                                          row_prev);
+                                          s_rsc[buf] + (Op::kScaled ? m * kTileRows : 0), lane, h, thr, gt, ld, li,
+                                          row_prev, a.parity);
                     pipe_step<Op, KP, NT>(acc1, acc0, bq, sb, s_frag[buf] + (m + 1) * TILE_U4,
                                           s_seed[buf] + (m + 1) * 8,
-                                          s_rsc[buf] + (Op::kScaled ? (m + 1) * kTileRows : 0), lane, h, thr, ld,
-                                          li, row_t);
+                                          s_rsc[buf] + (Op::kScaled ? (m + 1) * kTileRows : 0), lane, h, thr, gt,
+                                          ld, li, row_t, a.parity);
                     row_prev = row_t + kTileRows;
                 }
-                wait_vmcnt<(PD - 1) * LPS>();   // stage st + 1 has landed (this wave's part)
-                __syncthreads();                // ... every wave's part; stage st is consumed
+                // Stage st + 1 has landed (this wave's part); after the barrier
+                // every wave's part has, and stage st has been read by all (the
+                // tile reads complete before their MFMAs).  A plain barrier: a
+                // workgroup fence here would also wait for the prefetches.
+                wait_vmcnt<(PD - 1) * LPS>();
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_s_barrier();
+                asm volatile("" ::: "memory");
                 buf = (buf + 1) % NB;
             }
             wait_vmcnt<0>();                    // drain the loads past the end of the chunk
             __syncthreads();
-            tiles_select<KP, NT>(acc1, thr, ld, li, row_prev);
+            tiles_select<Op, KP, NT>(acc1, thr, gt, ld, li, row_prev, h, a.parity);
 
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {

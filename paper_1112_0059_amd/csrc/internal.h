@@ -40,6 +40,7 @@ struct DistArgs {
     const uint4 *frag;          // packed reference fragments
     const float *seed;          // per-row accumulator seed (norm), +inf on padding
     const int32_t *row_scale;   // fp8: per-row exponent bias (else null)
+    const uint32_t *parity;     // int8: per-tile mask of the rows' ||r - 128||^2 parities
     int64_t n_tiles;            // 32-row tiles in the padded index (multiple of 8)
     int32_t tiles_per_slice;    // multiple of 8
     int32_t n_slices;
@@ -74,7 +75,8 @@ struct RerankArgs {
 };
 
 struct FinishArgs {
-    const void *q;              // u8 queries (for ||q||^2)
+    const void *q;              // u8 queries (for ||q - shift||^2)
+    int32_t q_shift;            // 0, or 128 where the keys are those of r - 128 and q - 128
     const BatchDesc *bd;
     const int64_t *offsets;     // device [n_img + 1]
     const int32_t *labels;      // [n_refs]
@@ -113,6 +115,12 @@ int kp_bucket(int kp, int fmt);         // list length compiled for kp (0 = unsu
     X(bf16, OpBF16, FMT_BF16, 16) \
     X(bf16, OpBF16, FMT_BF16, 21) \
     X(bf16, OpBF16, FMT_BF16, 33) \
+    X(i8, OpI8, FMT_I8, 2)        \
+    X(i8, OpI8, FMT_I8, 6)        \
+    X(i8, OpI8, FMT_I8, 11)       \
+    X(i8, OpI8, FMT_I8, 16)       \
+    X(i8, OpI8, FMT_I8, 21)       \
+    X(i8, OpI8, FMT_I8, 33)       \
     X(fp8, OpFP8, FMT_FP8, 4)     \
     X(fp8, OpFP8, FMT_FP8, 8)     \
     X(fp8, OpFP8, FMT_FP8, 20)    \
@@ -121,6 +129,8 @@ int kp_bucket(int kp, int fmt);         // list length compiled for kp (0 = unsu
 // Upload-side packing.  refs_u8 / refs_f32 are device pointers.
 hipError_t launch_pack_u8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, int fmt,
                           uint4 *frag, float *seed, hipStream_t s);
+hipError_t launch_pack_i8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, uint4 *frag, int32_t *seed,
+                          uint32_t *parity, hipStream_t s);
 hipError_t launch_fp8_index(const float *refs, int64_t n_refs, int64_t n_pad, uint4 *frag, float *seed,
                             int32_t *row_scale, hipStream_t s);
 hipError_t launch_fp8_qprep(const float *q, const BatchDesc *bd, int64_t q_cap, uint4 *q8, int32_t *qsc,

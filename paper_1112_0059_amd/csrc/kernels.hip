@@ -14,8 +14,8 @@ namespace lnbnn {
 
 // ---------------------------------------------------------------------------
 // K0: packing of u8 references.  Fragment u = (tile * kSteps + s) * 64 + lane
-// holds the eight K elements lane `lane` supplies at step s for row
-// 32*tile + (lane & 31).
+// holds the K elements lane `lane` supplies at step s for row
+// 32*tile + (lane & 31) (eight FP16/BF16 values, or sixteen int8 values).
 // ---------------------------------------------------------------------------
 template <class Op>
 __global__ void k_pack_u8(const uint8_t *__restrict__ refs, int64_t n_refs, int64_t n_frag,
@@ -27,10 +27,38 @@ __global__ void k_pack_u8(const uint8_t *__restrict__ refs, int64_t n_refs, int6
         const int s = (int)((u >> 6) % Op::kSteps);
         const int64_t tile = (u >> 6) / Op::kSteps;
         const int64_t row = tile * kTileRows + (lane & 31);
-        uint2 raw = make_uint2(0u, 0u);
-        if (row < n_refs)
-            raw = *reinterpret_cast<const uint2 *>(refs + row * kDim + 16 * s + 8 * (lane >> 5));
-        frag[u] = Op::cvt8(raw, 1.0f);
+        const bool ok = row < n_refs;
+        frag[u] = Op::pack_frag(refs + (ok ? row : 0) * kDim, ok, s, lane >> 5);
+    }
+}
+
+// INT8 seeds: floor(||s||^2 / 2) + sum(s) with s = r - 128 (stored as the
+// int32 bit pattern), 2^30 on padding rows; and per 32-row tile the mask of
+// the rows' ||s||^2 parities (= parity of sum(r)).
+__global__ void k_seed_i8(const uint8_t *__restrict__ refs, int64_t n_refs, int64_t n_pad,
+                          int32_t *__restrict__ seed, uint32_t *__restrict__ parity)
+{
+    for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < n_pad;
+         row += (int64_t)gridDim.x * blockDim.x) {
+        int32_t sq = 0, sum = 0;
+        if (row < n_refs) {
+            const uint4 *p = reinterpret_cast<const uint4 *>(refs + row * kDim);
+            for (int c = 0; c < kDim / 16; ++c) {
+                const uint4 v = p[c];
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+                for (int i = 0; i < 4; ++i)
+                    for (int b = 0; b < 4; ++b) {
+                        const int32_t x = (int32_t)((w[i] >> (8 * b)) & 0xffu) - 128;
+                        sq += x * x;
+                        sum += x;
+                    }
+            }
+        }
+        seed[row] = row < n_refs ? (sq >> 1) + sum : OpI8::kPadSeed;
+        // one 32-row tile per wave half: bit (row & 31) of its mask
+        const uint64_t bits = __builtin_amdgcn_ballot_w64(row < n_refs && (sq & 1));
+        const int lane = threadIdx.x & 63;
+        if ((lane & 31) == 0) parity[row >> 5] = (uint32_t)(bits >> (lane & 32));
     }
 }
 
@@ -105,7 +133,7 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs a)
             dd[p] = bd;
             ii[p] = bi;
         }
-        // ||q||^2 turns d' back into the squared distance for the output lists
+        // ||q - shift||^2 turns the key back into the squared distance
         const uint4 *qr = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(a.q) + q * kDim);
         uint32_t qq = 0;
         for (int c = 0; c < kDim / 16; ++c) {
@@ -113,8 +141,8 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs a)
             const uint32_t w[4] = {v.x, v.y, v.z, v.w};
             for (int i = 0; i < 4; ++i)
                 for (int b = 0; b < 4; ++b) {
-                    const uint32_t x = (w[i] >> (8 * b)) & 0xffu;
-                    qq += x * x;
+                    const int32_t x = (int32_t)((w[i] >> (8 * b)) & 0xffu) - a.q_shift;
+                    qq += (uint32_t)(x * x);
                 }
         }
         // image of query q: last m with offsets[m] <= q
@@ -211,7 +239,7 @@ const char *variant_name(int v) { return (v >= 0 && v < kNumVariants) ? kVariant
 
 int kp_bucket(int kp, int fmt)
 {
-    if (fmt == FMT_F16 || fmt == FMT_BF16) {
+    if (fmt == FMT_F16 || fmt == FMT_BF16 || fmt == FMT_I8) {
         static const int b[] = {2, 6, 11, 16, 21, 33};
         for (int x : b)
             if (kp <= x) return x;
@@ -281,13 +309,16 @@ int grid_for(int64_t n, int block, int cap)
 hipError_t launch_pack_u8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, int fmt, uint4 *frag,
                           float *seed, hipStream_t s)
 {
-    const int64_t n_frag = (n_pad / kTileRows) * 8 * 64;
-    if (fmt == FMT_F16)
+    const int64_t n_tiles = n_pad / kTileRows;
+    if (fmt == FMT_F16) {
+        const int64_t n_frag = n_tiles * OpF16::kSteps * 64;
         k_pack_u8<OpF16><<<grid_for(n_frag, 256, 65536), 256, 0, s>>>(refs, n_refs, n_frag, frag);
-    else if (fmt == FMT_BF16)
+    } else if (fmt == FMT_BF16) {
+        const int64_t n_frag = n_tiles * OpBF16::kSteps * 64;
         k_pack_u8<OpBF16><<<grid_for(n_frag, 256, 65536), 256, 0, s>>>(refs, n_refs, n_frag, frag);
-    else
+    } else {
         return hipErrorInvalidValue;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (seed) {
@@ -295,6 +326,18 @@ hipError_t launch_pack_u8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, in
         e = hipGetLastError();
     }
     return e;
+}
+
+hipError_t launch_pack_i8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, uint4 *frag, int32_t *seed,
+                          uint32_t *parity, hipStream_t s)
+{
+    const int64_t n_frag = (n_pad / kTileRows) * OpI8::kSteps * 64;
+    k_pack_u8<OpI8><<<grid_for(n_frag, 256, 65536), 256, 0, s>>>(refs, n_refs, n_frag, frag);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // whole waves over whole tiles: n_pad is a multiple of 64
+    k_seed_i8<<<grid_for(n_pad, 256, 65536), 256, 0, s>>>(refs, n_refs, n_pad, seed, parity);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_u64(unsigned long long *p, int64_t cap, const BatchDesc *bd, int32_t n_classes,

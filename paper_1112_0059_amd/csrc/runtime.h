@@ -120,6 +120,7 @@ struct lnbnn_index {
     int32_t *labels = nullptr;
     float *ref_f32 = nullptr;       // FP8 mode: FP32 references for the re-rank
     int32_t *row_scale = nullptr;   // FP8 mode: E8M0 exponent of every padded row
+    uint32_t *parity = nullptr;     // INT8 mode: per-tile mask of ||r - 128||^2 parities
     int64_t device_bytes = 0;
 
     std::mutex mu;                                     // classify path (workspace, graphs)

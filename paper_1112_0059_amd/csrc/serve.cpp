@@ -114,7 +114,7 @@ static int setup_slot(Server *sv, Slot *sl)
     const int kmax = fp8 ? kMaxFp8K : LNBNN_MAX_K;
     // partial lists: the largest layout any (mode, k, batch bucket) plans
     int64_t part = 0;
-    for (int mode = 0; mode < 3; ++mode) {
+    for (int mode = 0; mode < 4; ++mode) {
         if (!(ix->modes & LNBNN_MODE_BIT(mode))) continue;
         for (int k = 1; k <= kmax; ++k) {
             const int len = dist_list_len(mode, k);
@@ -393,7 +393,6 @@ extern "C" int lnbnn_submit(lnbnn_index *ix, const void *queries, int dtype, int
     if (n_desc > 0 && !queries) return set_err(LNBNN_EINVAL, "NULL queries");
     if (mode < 0 || mode > 3 || !(ix->modes & LNBNN_MODE_BIT(mode)))
         return set_err(LNBNN_EINVAL, "mode %d is not materialised in this index", mode);
-    if (mode == LNBNN_EXACT_I8) return set_err(LNBNN_EINVAL, "mode %d is not built in this library", mode);
     const int want = mode == LNBNN_FP8_RERANK ? LNBNN_F32 : LNBNN_U8;
     if (dtype != want) return set_err(LNBNN_EINVAL, "dtype %d does not match mode %d", dtype, mode);
     if (k < 1 || k > LNBNN_MAX_K || (int64_t)k + 1 > ix->n_refs) return set_err(LNBNN_EINVAL, "bad k = %d", k);

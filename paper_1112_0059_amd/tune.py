@@ -14,7 +14,7 @@ import os
 import sys
 import time
 
-MODES = {"f16": 0, "bf16": 1, "fp8": 2}
+MODES = {"f16": 0, "bf16": 1, "fp8": 2, "i8": 3}
 
 
 def main(argv=None):

@@ -16,8 +16,11 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-MODES = [L.LNBNN_EXACT_F16, L.LNBNN_EXACT_BF16]
-BOTH = L.LNBNN_MODE_BIT(L.LNBNN_EXACT_F16) | L.LNBNN_MODE_BIT(L.LNBNN_EXACT_BF16)
+MODES = [L.LNBNN_EXACT_F16, L.LNBNN_EXACT_BF16, L.LNBNN_EXACT_I8]
+BOTH = (L.LNBNN_MODE_BIT(L.LNBNN_EXACT_F16) | L.LNBNN_MODE_BIT(L.LNBNN_EXACT_BF16) |
+        L.LNBNN_MODE_BIT(L.LNBNN_EXACT_I8))
+# the 16-bit form and the INT8 form (different kernels, keys and packing)
+FORMS = [L.LNBNN_EXACT_F16, L.LNBNN_EXACT_I8]
 
 
 def _say(*a):
@@ -57,42 +60,46 @@ def test_tiny_bit_exact(tiny, mode, k):
     _check_exact(got, ref[k], k)
 
 
+@pytest.mark.parametrize("mode", FORMS)
 @pytest.mark.parametrize("flags", [L.LNBNN_NO_GRAPH, L.LNBNN_PER_IMAGE_LAUNCH, L.LNBNN_TIMING])
-def test_tiny_launch_forms(tiny, flags):
+def test_tiny_launch_forms(tiny, flags, mode):
     cfg, R, labels, Q, off, ix, ref = tiny
-    _say(f"tiny flags={flags}")
-    got = L.lnbnn_classify(ix, Q, off, 10, L.LNBNN_EXACT_F16, flags=flags, want_neighbours=True)
+    _say(f"tiny flags={flags} mode={mode}")
+    got = L.lnbnn_classify(ix, Q, off, 10, mode, flags=flags, want_neighbours=True)
     _check_exact(got, ref[10], 10)
     if flags & L.LNBNN_TIMING:
         t = L.lnbnn_last_timing(ix)
         assert t["dist_kernel_ms"] > 0 and t["total_ms"] >= t["dist_kernel_ms"]
 
 
-def test_tiny_every_variant(tiny):
+@pytest.mark.parametrize("mode", FORMS)
+def test_tiny_every_variant(tiny, mode):
     cfg, R, labels, Q, off, ix, ref = tiny
     for v in range(L.lnbnn_num_variants()):
-        _say(f"variant {v}")
-        L.lnbnn_set_variant(ix, L.LNBNN_EXACT_F16, 10, v)
-        got = L.lnbnn_classify(ix, Q, off, 10, L.LNBNN_EXACT_F16, want_neighbours=True)
+        _say(f"variant {v} mode={mode}")
+        L.lnbnn_set_variant(ix, mode, 10, v)
+        got = L.lnbnn_classify(ix, Q, off, 10, mode, want_neighbours=True)
         _check_exact(got, ref[10], 10)
-    L.lnbnn_set_variant(ix, L.LNBNN_EXACT_F16, 10, -1)
+    L.lnbnn_set_variant(ix, mode, 10, -1)
 
 
+@pytest.mark.parametrize("mode", FORMS)
 @pytest.mark.parametrize("variant", [0, 4, 6])
-def test_tiny_chunked_walk(tiny, variant):
+def test_tiny_chunked_walk(tiny, variant, mode):
     """Few resident workgroups and short chunks: every workgroup owns several
     query blocks and saves/restores their lists between chunks."""
     cfg, R, labels, Q, off, ix, ref = tiny
-    _say(f"chunked walk variant {variant}")
-    L.lnbnn_set_tuning(ix, L.LNBNN_EXACT_F16, 10, variant=variant, chunk_tiles=8, max_workgroups=3)
+    _say(f"chunked walk variant {variant} mode={mode}")
+    L.lnbnn_set_tuning(ix, mode, 10, variant=variant, chunk_tiles=8, max_workgroups=3)
     try:
-        got = L.lnbnn_classify(ix, Q, off, 10, L.LNBNN_EXACT_F16, want_neighbours=True)
+        got = L.lnbnn_classify(ix, Q, off, 10, mode, want_neighbours=True)
         _check_exact(got, ref[10], 10)
     finally:
-        L.lnbnn_set_tuning(ix, L.LNBNN_EXACT_F16, 10)
+        L.lnbnn_set_tuning(ix, mode, 10)
 
 
-def test_device_pointers_and_graph_replays(tiny):
+@pytest.mark.parametrize("mode", FORMS)
+def test_device_pointers_and_graph_replays(tiny, mode):
     """Device tensors on torch's stream; the captured graph is replayed with
     eager work and synchronisations in between, and every replay matches."""
     import torch
@@ -107,20 +114,20 @@ def test_device_pointers_and_graph_replays(tiny):
         for t in out.values():
             t.fill_(-7)
         junk = torch.randn(1000, device="cuda").sum()      # eager work between replays
-        cls, tot, ni, nd = L.lnbnn_classify(ix, dq, off, 10, L.LNBNN_EXACT_F16,
-                                            want_neighbours=True, out=out)
+        cls, tot, ni, nd = L.lnbnn_classify(ix, dq, off, 10, mode, want_neighbours=True, out=out)
         torch.cuda.synchronize()
         _check_exact((cls.cpu().numpy(), tot.cpu().numpy(), ni.cpu().numpy(), nd.cpu().numpy()),
                      ref[10], 10)
         del junk
 
 
-def test_fp16_equals_bf16_tiny(tiny):
+def test_exact_modes_agree_tiny(tiny):
     cfg, R, labels, Q, off, ix, ref = tiny
     a = L.lnbnn_classify(ix, Q, off, 5, L.LNBNN_EXACT_F16, want_neighbours=True)
-    b = L.lnbnn_classify(ix, Q, off, 5, L.LNBNN_EXACT_BF16, want_neighbours=True)
-    for x, y in zip(a, b):
-        assert np.array_equal(x, y)
+    for mode in (L.LNBNN_EXACT_BF16, L.LNBNN_EXACT_I8):
+        b = L.lnbnn_classify(ix, Q, off, 5, mode, want_neighbours=True)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
 
 
 # ------------------------------------------------------------- edge cases
@@ -216,15 +223,16 @@ def test_mid_subset_bit_exact(mid, k):
 
 
 @pytest.mark.timeout(600)
-def test_mid_all_images_fp16_equals_bf16(mid):
+def test_mid_all_images_exact_modes_agree(mid):
     import torch
     cfg, R, labels, ix = mid
     Q, off, true_cls = synth.gen_queries(cfg)
     dq = torch.from_numpy(Q).cuda()
     _say("mid all images")
     a = L.lnbnn_classify(ix, dq, off, 10, L.LNBNN_EXACT_F16)
-    b = L.lnbnn_classify(ix, dq, off, 10, L.LNBNN_EXACT_BF16)
-    torch.cuda.synchronize()
-    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    for mode in (L.LNBNN_EXACT_BF16, L.LNBNN_EXACT_I8):
+        b = L.lnbnn_classify(ix, dq, off, 10, mode)
+        torch.cuda.synchronize()
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]), mode
     acc = float(np.mean(a[0].cpu().numpy() == true_cls))
     _say(f"mid accuracy (statistic) {acc:.3f}")
