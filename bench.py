@@ -3,9 +3,11 @@
 Workload (the configuration the headline metric is quoted on): a merged
 index of 256 classes x 30 training images x 2000 descriptors = 15.36M
 references (u8, 128-d), 512 query images of 500..4000 descriptors
-(1.15M query descriptors in total), k = 10, exact FP16 path.  One step =
-one classification of the whole batch: distance + top-(k+1) kernel,
-merge + class update, argmin, with the queries already resident in HBM.
+(1.15M query descriptors in total), k = 10, exact path on the INT8 matrix
+cores (bit-identical to the FP16 form, which is timed beside it for
+context).  One step = one classification of the whole batch: distance +
+top-(k+1) kernel, merge + class update, argmin, with the queries already
+resident in HBM.
 
 Prints one JSON line with the throughput (query descriptors/s), the
 roofline of the dominant kernel (distance + top-(k+1), timed with HIP events
@@ -30,8 +32,10 @@ sys.path.insert(0, ROOT)
 
 PEAK_MFMA_F16_TFLOPS = 2500.0       # MI355X dense FP16/BF16 matrix peak
 PEAK_MFMA_FP8_TFLOPS = 5000.0       # MI355X dense FP8 matrix peak
+PEAK_MFMA_I8_TOPS = 5000.0          # MI355X dense INT8 matrix peak (TOP/s)
+METRIC = "query descriptors/s at 15.4M refs k=10, exact vs FP8+rerank; p99 image ms"
 PEAK_HBM_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dist_topk_L_k10_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dist_topk_L_k10_i8_traffic.json")
 KERNEL_SRC = [os.path.join(ROOT, "paper_1112_0059_amd", "csrc", f) for f in ("dist_topk.h", "dist_inst.hip")]
 TUNING_CACHE = os.path.join(ROOT, "paper_1112_0059_amd", "tuning_cache.json")
 
@@ -81,22 +85,48 @@ def cpu_baseline(R, Q, target_s: float = 15.0):
                       f"k+1 = 11 nearest by brute force (oracle scan route); {dt:.1f} s"}
 
 
+def time_exact(args, L, torch, np, ix, dq, off, n_classes, mode, steps, warmup):
+    """Classify the whole batch `steps` times (after `warmup` untimed runs);
+    returns (wall s per step, mean distance-kernel ms, last timing, classes)."""
+    n_img = off.shape[0] - 1
+    out = {"class": torch.empty(n_img, dtype=torch.int32, device="cuda"),
+           "totals": torch.empty((n_img, n_classes), dtype=torch.int64, device="cuda")}
+
+    def step():
+        L.lnbnn_classify(ix, dq, off, args.k, mode, flags=L.LNBNN_TIMING, out=out)
+
+    for i in range(warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"mode {mode}: warmup {i + 1}/{warmup} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k1_ms = []
+    for i in range(steps):
+        step()
+        k1_ms.append(L.lnbnn_last_timing(ix)["dist_kernel_ms"])   # waits for this step
+        log(f"mode {mode}: step {i + 1}/{steps}: distance kernel {k1_ms[-1]:.1f} ms")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return dt, float(np.mean(k1_ms)), L.lnbnn_last_timing(ix), out["class"].cpu().numpy()
+
+
 def exact_leg(args, L, torch, np, synth):
     cfg = synth.CONFIGS["L"]
     t0 = time.perf_counter()
     R, labels = synth.gen_index(cfg)
     Q, off, true_cls = synth.gen_queries(cfg)
     log(f"generated {R.shape[0]} refs, {Q.shape[0]} queries in {time.perf_counter() - t0:.1f}s")
-    ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(L.LNBNN_EXACT_F16))
+    I8, F16 = L.LNBNN_EXACT_I8, L.LNBNN_EXACT_F16
+    ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(I8) | L.LNBNN_MODE_BIT(F16))
     dq = torch.from_numpy(Q).cuda()
     n_img = off.shape[0] - 1
-    tuned = None
+    tuned = {}
     if os.path.exists(TUNING_CACHE):
         # project autotuner: the cache holds the variant chosen on this
         # workload; a hit pins it without timing anything
-        tuned = L.lnbnn_autotune(ix, dq, off, args.k, L.LNBNN_EXACT_F16, cache_path=TUNING_CACHE)
-    out = {"class": torch.empty(n_img, dtype=torch.int32, device="cuda"),
-           "totals": torch.empty((n_img, cfg.n_classes), dtype=torch.int64, device="cuda")}
+        for mode in (I8, F16):
+            tuned[mode] = L.lnbnn_autotune(ix, dq, off, args.k, mode, cache_path=TUNING_CACHE)
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -105,54 +135,50 @@ def exact_leg(args, L, torch, np, synth):
         torch.cuda.synchronize()
         del src, dst
 
-    def step():
-        L.lnbnn_classify(ix, dq, off, args.k, L.LNBNN_EXACT_F16, flags=L.LNBNN_TIMING, out=out)
-
-    for i in range(args.warmup):
-        step()
-        torch.cuda.synchronize()
-        log(f"warmup {i + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    k1_ms = []
-    for i in range(args.steps):
-        step()
-        k1_ms.append(L.lnbnn_last_timing(ix)["dist_kernel_ms"])   # waits for this step
-        log(f"step {i + 1}/{args.steps}: distance kernel {k1_ms[-1]:.1f} ms")
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
     n_q = int(Q.shape[0])
-    acc = float(np.mean(out["class"].cpu().numpy() == true_cls))
-    timing = L.lnbnn_last_timing(ix)
-    k1 = float(np.mean(k1_ms)) / 1e3
     flop = 2.0 * 128 * cfg.n_refs * n_q
-    achieved = flop / k1 / 1e12
+    dt, k1_ms, timing, cls = time_exact(args, L, torch, np, ix, dq, off, cfg.n_classes, I8, args.steps, args.warmup)
+    achieved = flop / (k1_ms / 1e3) / 1e12
     res = {
-        "metric": "query descriptors/s at 15.4M refs k=10 (exact FP16 path)",
-        "value": n_q * args.steps / dt,
+        "metric": METRIC,
+        "value": n_q / dt,
         "unit": "query descriptors/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
+        "ms_per_step": dt * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f16",
+        "dtype": "i8",
         "data": "synthetic",
         "config": {"workload": "L: merged index 256 classes x 30 images x 2000 u8 128-d "
                                "descriptors = 15.36M refs; 512 query images of 500..4000 "
-                               f"descriptors ({n_q} total); k={args.k}; exact FP16 MFMA path",
+                               f"descriptors ({n_q} total); k={args.k}; exact path on the INT8 "
+                               "matrix cores (INT32 accumulation, bit-exact)",
                    "n_refs": cfg.n_refs, "n_query_desc": n_q, "n_images": n_img, "k": args.k,
+                   "mode": "EXACT_I8",
                    "variant": L.lnbnn_variant_name(timing["tile_variant"]),
-                   "autotuned": tuned is not None,
+                   "autotuned": I8 in tuned,
                    "slices": timing["slices"]},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_F16_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_F16_TFLOPS,
-                     "traffic": traffic_per_launch(), "kernel": "k_dist_topk",
-                     "kernel_ms": k1 * 1e3, "algorithmic_flop_per_launch": flop},
-        "accuracy_statistic": acc,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_I8_TOPS,
+                     "unit": "TOP/s", "frac": achieved / PEAK_MFMA_I8_TOPS,
+                     "traffic": traffic_per_launch(), "kernel": "k_dist_topk<OpI8, 11, ...>",
+                     "kernel_ms": k1_ms, "algorithmic_ops_per_launch": flop},
+        "accuracy_statistic": float(np.mean(cls == true_cls)),
     }
+    if not args.no_f16:
+        # the same exact classification on the FP16 matrix cores, for context
+        steps16 = max(1, min(args.steps, 2))
+        dt16, k1_16, t16, cls16 = time_exact(args, L, torch, np, ix, dq, off, cfg.n_classes, F16, steps16, 1)
+        a16 = flop / (k1_16 / 1e3) / 1e12
+        res["exact_f16"] = {"value": n_q / dt16, "unit": "query descriptors/s", "steps": steps16,
+                            "ms_per_step": dt16 * 1e3, "dtype": "f16",
+                            "variant": L.lnbnn_variant_name(t16["tile_variant"]),
+                            "same_classes_as_i8": bool(np.array_equal(cls16, cls)),
+                            "roofline": {"bound": "mfma", "achieved": a16, "peak": PEAK_MFMA_F16_TFLOPS,
+                                         "unit": "TFLOP/s", "frac": a16 / PEAK_MFMA_F16_TFLOPS,
+                                         "kernel_ms": k1_16}}
     return res, ix, R, Q, cfg
 
 
@@ -203,7 +229,7 @@ def fp8_leg(args, L, torch, np, synth):
     achieved = flop / k1 / 1e12
     del R
     return {
-        "metric": "query descriptors/s at 15.4M refs k=10 (FP8 candidates 4k + exact FP32 re-rank)",
+        "metric": "query descriptors/s at 15.4M refs k=10 (FP8 candidates + exact FP32 re-rank)",
         "value": n_q * steps / dt, "unit": "query descriptors/s", "steps": steps,
         "ms_per_step": dt / steps * 1e3, "dtype": "fp8 e4m3 -> f32",
         "config": {"workload": "P: 15.36M float32 refs (L structure, unit-norm ReLU descriptors, noise 0.08), "
@@ -224,13 +250,13 @@ def serving_leg(args, L, torch, np, synth, ix_exact, ix_fp8, mu_exact_qps, mu_fp
     alone with per-image launches, in arrival order."""
     import threading
     from collections import deque
-    rho, n_warm, n_meas = 0.7, 40, args.serve_requests
+    n_warm, n_meas = args.serve_warmup, args.serve_requests
     n_req = n_warm + n_meas
     unit_arrivals, counts = synth.request_stream(n_req, 1.0, seed=3000)
-    lam = rho * mu_exact_qps / float(np.mean(counts))     # requests/s
-    arrivals = unit_arrivals / lam
-    out = {"offered_load": rho, "arrival_rate_per_s": lam, "requests_measured": n_meas,
-           "requests_warmup": n_warm, "trace": "Poisson arrivals; n ~ clip(round(LogNormal(ln 1500, 0.6)), 100, 8000)"}
+    mu_img = mu_exact_qps / float(np.mean(counts))        # batched exact capacity, images/s
+    out = {"capacity_images_per_s": mu_img, "requests_measured": n_meas, "requests_warmup": n_warm,
+           "trace": "Poisson arrivals at rho x capacity; n ~ clip(round(LogNormal(ln 1500, 0.6)), 100, 8000)"}
+    arrivals = unit_arrivals
 
     def run_batched(ix, mode, Qr, offr):
         tickets = [None] * n_req
@@ -300,15 +326,23 @@ def serving_leg(args, L, torch, np, synth, ix_exact, ix_fp8, mu_exact_qps, mu_fp
 
     cfgL = synth.CONFIGS["L"]
     Qr, offr = synth.gen_requests(cfgL, counts)
-    log(f"serving: {n_req} requests, {offr[-1]} descriptors, rate {lam:.1f}/s")
-    out["batched_exact_f16"] = summary(*run_batched(ix_exact, L.LNBNN_EXACT_F16, Qr, offr))
-    log(f"serving batched exact: {out['batched_exact_f16']}")
-    out["plain_per_image_exact_f16"] = summary(*run_plain(ix_exact, L.LNBNN_EXACT_F16, Qr, offr))
-    log(f"serving plain exact: {out['plain_per_image_exact_f16']}")
+    Qf = offf = None
     if ix_fp8 is not None:
         Qf, offf = synth.gen_requests(synth.CONFIGS["P"], counts)
-        out["batched_fp8_rerank"] = summary(*run_batched(ix_fp8, L.LNBNN_FP8_RERANK, Qf, offf))
-        log(f"serving batched fp8: {out['batched_fp8_rerank']}")
+    for rho in (0.7, 0.9):
+        lam = rho * mu_img
+        arrivals = unit_arrivals / lam
+        r = {"offered_load": rho, "arrival_rate_per_s": lam}
+        log(f"serving rho={rho}: {n_req} requests, {offr[-1]} descriptors, rate {lam:.1f}/s")
+        r["batched_exact"] = summary(*run_batched(ix_exact, L.LNBNN_EXACT_I8, Qr, offr))
+        log(f"serving batched exact: {r['batched_exact']}")
+        if Qf is not None:
+            r["batched_fp8_rerank"] = summary(*run_batched(ix_fp8, L.LNBNN_FP8_RERANK, Qf, offf))
+            log(f"serving batched fp8: {r['batched_fp8_rerank']}")
+        if rho == 0.7:
+            r["plain_per_image_exact"] = summary(*run_plain(ix_exact, L.LNBNN_EXACT_I8, Qr, offr))
+            log(f"serving plain exact: {r['plain_per_image_exact']}")
+        out[f"rho_{rho}"] = r
     return out
 
 
@@ -320,8 +354,10 @@ def main():
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--legs", default="exact,fp8,serving",
                     help="comma list: exact (always), fp8, serving")
-    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f16", action="store_true", help="skip the FP16 context timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -352,6 +388,7 @@ def main():
         try:
             mu8 = res.get("fp8_rerank", {}).get("value")
             res["serving"] = serving_leg(args, L, torch, np, synth, ix, ix8, res["value"], mu8)
+            res["p99_image_ms"] = res["serving"]["rho_0.7"]["batched_exact"]["p99_ms"]
         except Exception as e:
             res["serving"] = {"error": repr(e)}
     if ix8 is not None:
