@@ -674,6 +674,8 @@ static void *pick_variant(int v)
             case 1: return kernel_ptr<Op, KP, 2, 2, 4, 4>();
             case 4: return kernel_ptr<Op, KP, 2, 4, 8, 4>();
             case 5: return kernel_ptr<Op, KP, 2, 2, 8, 8>();
+            case 8: return kernel_ptr<Op, KP, 2, 8, 8, 4>();
+            case 9: return kernel_ptr<Op, KP, 2, 4, 8, 8>();
             }
         }
     } else if constexpr (KP <= 16) {
@@ -684,6 +686,12 @@ static void *pick_variant(int v)
         case 4: return kernel_ptr<Op, KP, 2, 4, 8, 4>();
         case 5: return kernel_ptr<Op, KP, 2, 2, 8, 8>();
         case 7: return kernel_ptr<Op, KP, 2, 4, 4, 3>();
+        }
+        if constexpr (Op::kSteps * Op::kAU == 4) {      // 4 KB tiles
+            switch (v) {
+            case 8: return kernel_ptr<Op, KP, 2, 8, 8, 4>();
+            case 9: return kernel_ptr<Op, KP, 2, 4, 8, 8>();
+            }
         }
     }
     return nullptr;

@@ -228,9 +228,12 @@ static const Variant kVariants[] = {
     {2, 2, 8, 8},   // 5
     {1, 4, 8, 4},   // 6
     {2, 4, 4, 3},   // 7
+    {2, 8, 8, 4},   // 8  (4 KB tiles only: INT8, FP8)
+    {2, 4, 8, 8},   // 9  (4 KB tiles only: INT8, FP8)
 };
 static const char *kVariantNames[] = {"w4_nt1_mt2_nb4", "w4_nt2_mt2_nb4", "w4_nt2_mt4_nb2", "w4_nt2_mt2_nb2",
-                                      "w8_nt2_mt4_nb4", "w8_nt2_mt2_nb8", "w8_nt1_mt4_nb4", "w4_nt2_mt4_nb3"};
+                                      "w8_nt2_mt4_nb4", "w8_nt2_mt2_nb8", "w8_nt1_mt4_nb4", "w4_nt2_mt4_nb3",
+                                      "w8_nt2_mt8_nb4", "w8_nt2_mt4_nb8"};
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int num_variants() { return kNumVariants; }
@@ -256,7 +259,9 @@ bool variant_supports(int v, int fmt, int kp)
     if (v < 0 || v >= kNumVariants) return false;
     const int b = kp_bucket(kp, fmt);
     if (b == 0) return false;
-    if (fmt == FMT_FP8) return v == 0 || v == 6 || ((v == 1 || v == 4 || v == 5) && b <= 20);
+    // the deep stage variants need the 4 KB tiles of the 8-bit formats
+    if ((v == 8 || v == 9) && (fmt == FMT_F16 || fmt == FMT_BF16)) return false;
+    if (fmt == FMT_FP8) return v == 0 || v == 6 || ((v == 1 || v == 4 || v == 5 || v >= 8) && b <= 20);
     return kVariants[v].nt == 1 || b <= 16;
 }
 

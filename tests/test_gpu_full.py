@@ -1,0 +1,170 @@
+"""Full-size checks at the benchmarked workloads, in the launch configuration
+the benchmark times (device pointers, one batched launch sequence).
+
+Exact path, 15.36M references, 512 query images, k = 10 (INT8 mode):
+  * every returned neighbour carries its exact squared distance and every
+    list is in (distance, index) order (all 1.16M query descriptors);
+  * the image totals and classes follow from the returned lists by
+    Algorithm 2's update (re-derived here, all 512 images);
+  * sampled descriptors' neighbour lists and one whole image's totals and
+    class equal the oracle's.
+FP8 + re-rank, float descriptors of the same shape:
+  * every returned distance is the FP32 direct-form distance within the
+    rounding bound, lists in (distance, index) order;
+  * sampled descriptors' recall and one whole image's decision against the
+    FP64 oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1112_0059_amd as L
+import synth
+
+pytestmark = pytest.mark.gpu
+GAMMA = 130 * 2.0 ** -24
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _sorted_lists(ni, nd):
+    dd, di = np.diff(nd, axis=1), np.diff(ni.astype(np.int64), axis=1)
+    return np.all((dd > 0) | ((dd == 0) & (di > 0)))
+
+
+def _totals_from_lists(ni, nd, labels, n_classes, off, k):
+    """Algorithm 2's update from given neighbour lists (numpy, exact int64):
+    each class met among the first k, at its first occurrence, adds its
+    distance minus the (k+1)-th."""
+    n_img = len(off) - 1
+    lab = labels[ni[:, :k]]                                      # [n, k]
+    d = nd.astype(np.int64)
+    delta = d[:, :k] - d[:, k:k + 1]
+    first = np.ones_like(lab, bool)
+    for j in range(1, k):
+        first[:, j] = np.all(lab[:, :j] != lab[:, j:j + 1], axis=1)
+    img = np.repeat(np.arange(n_img), np.diff(off))
+    T = np.zeros((n_img, n_classes), np.int64)
+    rows = np.repeat(img, k)[first.ravel()]
+    np.add.at(T, (rows, lab.ravel()[first.ravel()]), delta.ravel()[first.ravel()])
+    return T
+
+
+@pytest.fixture(scope="module")
+def big():
+    import torch
+    cfg = synth.CONFIGS["L"]
+    _say("generating the 15.36M-reference index")
+    R, labels = synth.gen_index(cfg)
+    Q, off, true_cls = synth.gen_queries(cfg)
+    ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(L.LNBNN_EXACT_I8))
+    dq = torch.from_numpy(Q).cuda()
+    _say("classifying 512 images")
+    cls, tot, ni, nd = L.lnbnn_classify(ix, dq, off, 10, L.LNBNN_EXACT_I8, want_neighbours=True)
+    torch.cuda.synchronize()
+    got = (cls.cpu().numpy(), tot.cpu().numpy(), ni.cpu().numpy(), nd.cpu().numpy())
+    yield cfg, R, labels, Q, off, ix, got
+    ix.free()
+
+
+@pytest.mark.timeout(900)
+def test_full_exact_lists_are_exact_distances(big):
+    cfg, R, labels, Q, off, ix, (cls, tot, ni, nd) = big
+    k = 10
+    assert ni.shape == (Q.shape[0], k + 1) and ni.min() >= 0 and ni.max() < cfg.n_refs
+    assert _sorted_lists(ni, nd)
+    _say("recomputing 12.7M neighbour distances")
+    for s in range(0, Q.shape[0], 1 << 16):
+        q = Q[s:s + (1 << 16)].astype(np.int32)
+        r = R[ni[s:s + (1 << 16)]].astype(np.int32)              # [b, k+1, 128]
+        d = np.sum((r - q[:, None, :]) ** 2, axis=2)
+        assert np.array_equal(d, nd[s:s + (1 << 16)].astype(np.int64)), s
+
+
+@pytest.mark.timeout(900)
+def test_full_exact_totals_follow_from_lists(big):
+    cfg, R, labels, Q, off, ix, (cls, tot, ni, nd) = big
+    T = _totals_from_lists(ni, nd, labels, cfg.n_classes, off, 10)
+    assert np.array_equal(T, tot)
+    assert np.all(tot <= 0)
+    best = np.argmin(tot, axis=1)                               # lowest class on ties
+    assert np.array_equal(best, cls)
+
+
+@pytest.mark.timeout(900)
+def test_full_exact_sampled_against_oracle(big):
+    """64 sampled descriptors (4 images x 16) and the smallest whole image."""
+    cfg, R, labels, Q, off, ix, (cls, tot, ni, nd) = big
+    imgs = [3, 200, 377, 511]
+    sel = np.concatenate([np.arange(off[m], off[m] + 16) for m in imgs])
+    _say("oracle kNN for 64 sampled descriptors")
+    wi, wd = oracle.knn_expanded(Q[sel], R, 11)
+    assert np.array_equal(ni[sel], wi) and np.array_equal(nd[sel].astype(np.int64), wd)
+    m = int(np.argmin(np.diff(off)))
+    s, e = int(off[m]), int(off[m + 1])
+    _say(f"oracle classification of image {m} ({e - s} descriptors)")
+    wt, wc, wi, wd = oracle.classify(Q[s:e], R, labels, cfg.n_classes, np.array([0, e - s]), 10)
+    assert np.array_equal(ni[s:e], wi)
+    assert np.array_equal(tot[m], wt[0]) and cls[m] == wc[0]
+
+
+@pytest.fixture(scope="module")
+def bigf():
+    import torch
+    cfg = synth.CONFIGS["P"]
+    _say("generating the 15.36M-reference float index")
+    R, labels = synth.gen_index(cfg)
+    Q, off, true_cls = synth.gen_queries(cfg)
+    ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(L.LNBNN_FP8_RERANK))
+    dq = torch.from_numpy(Q).cuda()
+    _say("classifying 512 float images")
+    cls, tot, ni, nd = L.lnbnn_classify(ix, dq, off, 10, L.LNBNN_FP8_RERANK, want_neighbours=True)
+    torch.cuda.synchronize()
+    got = (cls.cpu().numpy(), tot.cpu().numpy(), ni.cpu().numpy(), nd.cpu().numpy())
+    yield cfg, R, labels, Q, off, ix, got, true_cls
+    ix.free()
+
+
+@pytest.mark.timeout(900)
+def test_full_fp8_distances_and_order(bigf):
+    cfg, R, labels, Q, off, ix, (cls, tot, ni, nd), true_cls = bigf
+    assert ni.min() >= 0 and ni.max() < cfg.n_refs
+    assert _sorted_lists(ni, nd)
+    _say("recomputing float neighbour distances")
+    for s in range(0, Q.shape[0], 1 << 15):
+        q = Q[s:s + (1 << 15)].astype(np.float64)
+        r = R[ni[s:s + (1 << 15)]].astype(np.float64)
+        d = np.sum((r - q[:, None, :]) ** 2, axis=2)
+        assert np.all(np.abs(nd[s:s + (1 << 15)] - d) <= GAMMA * d + 1e-30), s
+    # statistic, not a pin: the synthetic images' true classes
+    _say(f"accuracy (statistic) {np.mean(cls == true_cls):.4f}")
+
+
+@pytest.mark.timeout(900)
+def test_full_fp8_sampled_against_oracle(bigf):
+    cfg, R, labels, Q, off, ix, (cls, tot, ni, nd), true_cls = bigf
+    imgs = [3, 200, 377, 511]
+    sel = np.concatenate([np.arange(off[m], off[m] + 16) for m in imgs])
+    _say("FP64 oracle kNN for 64 sampled float descriptors")
+    wi, wd = oracle.knn_expanded(Q[sel], R, 11)
+    recall = np.mean([len(set(ni[i]) & set(wi[j])) / 11 for j, i in enumerate(sel)])
+    _say(f"recall {recall:.4f}")
+    assert recall >= 0.995
+    m = int(np.argmin(np.diff(off)))
+    s, e = int(off[m]), int(off[m + 1])
+    _say(f"FP64 oracle classification of image {m} ({e - s} descriptors)")
+    wi, wd = oracle.knn_expanded(Q[s:e], R, 11)
+    wt, wc = oracle.local_nbnn(wi, wd, 10, labels, cfg.n_classes, np.array([0, e - s]))
+    same = np.all(ni[s:e] == wi, axis=1)
+    _say(f"identical lists {same.mean():.4f}")
+    assert cls[m] == wc[0]
+    margin = np.sort(wt[0])[1] - np.sort(wt[0])[0]
+    err = np.max(np.abs(tot[m] - wt[0]))
+    _say(f"score error {err:.3e} (oracle top-2 margin {margin:.3e})")
+    if np.all(same):
+        assert err <= GAMMA * 2 * np.abs(wt[0]).sum() + 1e-9

@@ -77,7 +77,11 @@ def test_tiny_every_variant(tiny, mode):
     cfg, R, labels, Q, off, ix, ref = tiny
     for v in range(L.lnbnn_num_variants()):
         _say(f"variant {v} mode={mode}")
-        L.lnbnn_set_variant(ix, mode, 10, v)
+        try:
+            L.lnbnn_set_variant(ix, mode, 10, v)
+        except L.LnbnnError:          # not built for this operand format
+            assert mode == L.LNBNN_EXACT_F16 and v >= 8
+            continue
         got = L.lnbnn_classify(ix, Q, off, 10, mode, want_neighbours=True)
         _check_exact(got, ref[10], 10)
     L.lnbnn_set_variant(ix, mode, 10, -1)
