@@ -163,11 +163,13 @@ int lnbnn_last_timing(const lnbnn_index *ix, lnbnn_timing *out);
 /*
  * Project autotuner for the batched launch: times every kernel variant that
  * can serve (mode, k) on the given query batch (same arguments as a
- * LNBNN_DEVICE_PTRS classify without outputs) and keeps the fastest for
- * this index, keyed by (n_refs, dim, k bucket, mode).  If `cache_path` is
- * not NULL the choice is merged into that JSON file, and a later call with
- * the same key reads it back instead of timing again.  Results do not depend
- * on the variant: every variant computes the same exact selection.
+ * LNBNN_DEVICE_PTRS classify without outputs), then chunk lengths of the
+ * chunk-major walk (lnbnn_tuning.chunk_tiles) for the two fastest, and keeps
+ * the fastest setting for this index, keyed by (arch, n_refs, dim, k bucket,
+ * mode).  If `cache_path` is not NULL the choice is merged into that JSON
+ * file (value = variant | chunk_tiles << 8), and a later call with the same
+ * key reads it back instead of timing again.  Results do not depend on the
+ * setting: every variant and walk computes the same exact selection.
  * `best_variant` (may be NULL) receives the chosen variant id.
  */
 int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtype,

@@ -888,10 +888,13 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
     if (cache_path) {
         auto m = read_cache(cache_path);
         auto it = m.find(key.str());
-        if (it != m.end() && variant_supports(it->second, fmt, dist_list_len(mode, k))) {
+        // cache value: variant | chunk_tiles << 8 (chunk 0 = whole slice)
+        const int cv = it != m.end() ? it->second & 0xff : -1;
+        const int cc = it != m.end() ? it->second >> 8 : 0;
+        if (it != m.end() && variant_supports(cv, fmt, dist_list_len(mode, k)) && cc >= 0 && cc % 8 == 0) {
             std::lock_guard<std::mutex> lock(ix->plan_mu);
-            ix->pinned[{mode, kpb}] = lnbnn_tuning{it->second, 0, 0};
-            if (best_variant) *best_variant = it->second;
+            ix->pinned[{mode, kpb}] = lnbnn_tuning{cv, cc, 0};
+            if (best_variant) *best_variant = cv;
             return LNBNN_OK;
         }
     }
@@ -899,36 +902,57 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
     std::vector<int32_t> cls(n_images);
     int32_t *d_cls = nullptr;
     LN_HIP(hipMalloc((void **)&d_cls, std::max<int32_t>(1, n_images) * 4));
-    int best = -1;
-    double best_ms = 1e30;
-    const int list_len = dist_list_len(mode, k);
-    for (int v = 0; v < num_variants(); ++v) {
-        if (!variant_supports(v, fmt, list_len)) continue;
-        if ((rc = lnbnn_set_variant(ix, mode, k, v))) break;
+    // distance-kernel time of one (variant, chunk) setting: mean of two runs
+    // after one warm-up run
+    auto time_setting = [&](int v, int chunk, double *ms) {
+        lnbnn_tuning t{v, chunk, 0};
+        int r = lnbnn_set_tuning(ix, mode, k, &t);
         double tot = 0;
-        for (int rep = 0; rep < 3 && !rc; ++rep) {
-            rc = lnbnn_classify(ix, queries_dev, dtype, img_offsets, n_images, k, mode,
-                                LNBNN_DEVICE_PTRS | LNBNN_NO_GRAPH | LNBNN_TIMING, d_cls, nullptr, nullptr, nullptr,
-                                stream);
-            if (!rc && rep > 0) tot += ix->last_timing.dist_kernel_ms;
+        for (int rep = 0; rep < 3 && !r; ++rep) {
+            r = lnbnn_classify(ix, queries_dev, dtype, img_offsets, n_images, k, mode,
+                               LNBNN_DEVICE_PTRS | LNBNN_NO_GRAPH | LNBNN_TIMING, d_cls, nullptr, nullptr, nullptr,
+                               stream);
+            if (!r && rep > 0) tot += ix->last_timing.dist_kernel_ms;
         }
-        if (rc) break;
-        if (tot / 2 < best_ms) {
-            best_ms = tot / 2;
-            best = v;
+        *ms = tot / 2;
+        return r;
+    };
+    // every variant with whole-slice sweeps, then chunk lengths (chunk-major
+    // walk: the workgroups of an XCD sweep the same references together) for
+    // the two fastest variants
+    std::vector<std::pair<double, int>> by_variant;
+    const int list_len = dist_list_len(mode, k);
+    for (int v = 0; v < num_variants() && !rc; ++v) {
+        if (!variant_supports(v, fmt, list_len)) continue;
+        double ms = 0;
+        if (!(rc = time_setting(v, 0, &ms))) by_variant.push_back({ms, v});
+    }
+    std::sort(by_variant.begin(), by_variant.end());
+    int best = by_variant.empty() ? -1 : by_variant[0].second, best_chunk = 0;
+    double best_ms = by_variant.empty() ? 1e30 : by_variant[0].first;
+    for (size_t i = 0; i < by_variant.size() && i < 2 && !rc; ++i) {
+        for (int chunk : {2048, 4096, 8192}) {
+            double ms = 0;
+            if ((rc = time_setting(by_variant[i].second, chunk, &ms))) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = by_variant[i].second;
+                best_chunk = chunk;
+            }
         }
     }
     (void)hipFree(d_cls);
     (void)n_q;
-    if (rc) {
+    if (rc || best < 0) {
         lnbnn_set_variant(ix, mode, k, -1);
-        return rc;
+        return rc ? rc : set_err(LNBNN_EINVAL, "no variant can serve mode %d with k = %d", mode, k);
     }
-    lnbnn_set_variant(ix, mode, k, best);
+    lnbnn_tuning bt{best, best_chunk, 0};
+    lnbnn_set_tuning(ix, mode, k, &bt);
     if (best_variant) *best_variant = best;
     if (cache_path) {
         auto m = read_cache(cache_path);
-        m[key.str()] = best;
+        m[key.str()] = best | (best_chunk << 8);
         write_cache(cache_path, m);
     }
     return LNBNN_OK;

@@ -72,6 +72,7 @@ static __device__ __forceinline__ int min16(const i32x16 &a)
 // compares a tile's smallest key with the list's KP-th key.
 struct FloatKeys {
     using acc_t = f32x16;
+    using gate_t = float;
     static constexpr bool kParity = false;
     static __device__ __forceinline__ float init() { return __builtin_inff(); }
     static __device__ __forceinline__ float gate_min(const f32x16 &acc) { return min16(acc); }
@@ -202,12 +203,17 @@ struct OpI8 {
     static constexpr int kAU = 1;
     static constexpr bool kScaled = false;
     using acc_t = i32x16;
+    using gate_t = int;
     static constexpr bool kParity = true;
     static constexpr int kPadSeed = 1 << 30;
     static __device__ __forceinline__ int init() { return 0x7fffffff; }
-    static __device__ __forceinline__ float gate_min(const i32x16 &acc) { return (float)min16(acc); }
-    // key = 2D + b < thr implies D < ceil(thr / 2)
-    static __device__ __forceinline__ float gate_thr(float thr) { return __builtin_ceilf(0.5f * thr); }
+    static __device__ __forceinline__ int gate_min(const i32x16 &acc) { return min16(acc); }
+    // key = 2D + b < thr implies D < ceil(thr / 2); no bound while the list
+    // is not full (thr = +inf)
+    static __device__ __forceinline__ int gate_thr(float thr)
+    {
+        return thr < 1e30f ? (int)__builtin_ceilf(0.5f * thr) : 0x7fffffff;
+    }
     static __device__ __forceinline__ float key(const i32x16 &acc, int r, uint32_t parity, int h)
     {
         const int d = acc[r];
@@ -289,7 +295,8 @@ static __device__ __forceinline__ uint32_t load_uniform(const uint32_t *p, int i
 // Insert every key of one tile that beats the list's current KP-th key;
 // gt is the gate threshold that goes with the list's new KP-th key.
 template <class Op, int KP>
-static __device__ __forceinline__ void tile_insert(const typename Op::acc_t &acc, float &thr, float &gt,
+static __device__ __forceinline__ void tile_insert(const typename Op::acc_t &acc, float &thr,
+                                                   typename Op::gate_t &gt,
                                                    float (&ld)[KP], int (&li)[KP], int row0, int h,
                                                    const uint32_t *parity)
 {
@@ -314,7 +321,7 @@ static __device__ __forceinline__ void tile_insert(const typename Op::acc_t &acc
 // are computed before any branch so they can overlap the next MFMA chain.
 template <class Op, int KP, int NT>
 static __device__ __forceinline__ void tiles_select(const typename Op::acc_t (&acc)[NT], float (&thr)[NT],
-                                                    float (&gt)[NT], float (&ld)[NT][KP], int (&li)[NT][KP],
+                                                    typename Op::gate_t (&gt)[NT], float (&ld)[NT][KP], int (&li)[NT][KP],
                                                     int row0, int h, const uint32_t *parity)
 {
     bool any[NT];
@@ -322,7 +329,7 @@ static __device__ __forceinline__ void tiles_select(const typename Op::acc_t (&a
     for (int nt = 0; nt < NT; ++nt) any[nt] = __builtin_amdgcn_ballot_w64(Op::gate_min(acc[nt]) < gt[nt]) != 0;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
-        if (any[nt]) tile_insert<Op, KP>(acc[nt], thr[nt], gt[nt], ld[nt], li[nt], row0, h, parity);
+        if (__builtin_expect(any[nt], 0)) tile_insert<Op, KP>(acc[nt], thr[nt], gt[nt], ld[nt], li[nt], row0, h, parity);
 }
 
 typedef __attribute__((address_space(1))) const void *gmem_ptr;
@@ -345,6 +352,30 @@ struct StageLoads {
     static constexpr int total = frag + 1 + (Op::kScaled ? 1 : 0);
 };
 
+static __device__ __forceinline__ uint32_t lds_addr(const void *p)
+{
+    return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const void *)p;
+}
+
+// Asynchronous global-to-LDS copies (global_load_lds: every lane moves its
+// bytes to M0 + lane * size), written as inline assembly so that the
+// compiler does not count them against its own LDS accesses: it would
+// otherwise make every LDS read wait for all copies in flight, including
+// the prefetch of later stages.  The stage loop orders each read after the
+// copy it needs with its own vmcnt wait and barrier.  One wait state
+// separates the M0 write from the copy.
+static __device__ __forceinline__ void dma16(const void *src, uint32_t lds)
+{
+    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off"
+                 :: "s"(lds), "v"(src) : "memory", "m0");
+}
+
+static __device__ __forceinline__ void dma4(const void *src, uint32_t lds)
+{
+    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dword %1, off"
+                 :: "s"(lds), "v"(src) : "memory", "m0");
+}
+
 template <class Op, int MT, int W, int TILE_U4>
 static __device__ __forceinline__ void stage_copy(const uint4 *src, uint4 *dst, const float *seed_src, float *seed_dst,
                                                   const int32_t *rsc_src, int32_t *rsc_dst, int wave, int lane)
@@ -353,14 +384,12 @@ static __device__ __forceinline__ void stage_copy(const uint4 *src, uint4 *dst, 
 #pragma unroll
     for (int c = 0; c < SL::frag; ++c) {
         const int chunk = c * W + wave;
-        __builtin_amdgcn_global_load_lds((gmem_ptr)(src + chunk * 64 + lane), (lds_ptr)(dst + chunk * 64), 16, 0, 0);
+        dma16(src + chunk * 64 + lane, lds_addr(dst + chunk * 64));
     }
     const int s0 = wave * SL::seeds_per_wave;
-    if (lane < SL::seeds_per_wave)
-        __builtin_amdgcn_global_load_lds((gmem_ptr)(seed_src + s0 + lane), (lds_ptr)(seed_dst + s0), 4, 0, 0);
+    if (lane < SL::seeds_per_wave) dma4(seed_src + s0 + lane, lds_addr(seed_dst + s0));
     if constexpr (Op::kScaled) {
-        if (lane < SL::seeds_per_wave)
-            __builtin_amdgcn_global_load_lds((gmem_ptr)(rsc_src + s0 + lane), (lds_ptr)(rsc_dst + s0), 4, 0, 0);
+        if (lane < SL::seeds_per_wave) dma4(rsc_src + s0 + lane, lds_addr(rsc_dst + s0));
     }
 }
 
@@ -376,10 +405,6 @@ static __device__ __forceinline__ void wait_vmcnt()
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-static __device__ __forceinline__ uint32_t lds_addr(const void *p)
-{
-    return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const void *)p;
-}
 
 // All LDS reads of one tile (A fragments, seeds, row scales) as one block
 // that also waits for them.  The compiler cannot tell which of the stage
@@ -479,7 +504,7 @@ static __device__ __forceinline__ void pipe_step(typename Op::acc_t (&acc_new)[N
                                                  const typename Op::acc_t (&acc_old)[NT],
                                                  const uint4 (&bq)[NT][Op::kSteps][Op::kAU], const int (&sb)[NT],
                                                  const uint4 *frag, const float4 *seed, const int32_t *rsc, int lane,
-                                                 int h, float (&thr)[NT], float (&gt)[NT], float (&ld)[NT][KP],
+                                                 int h, float (&thr)[NT], typename Op::gate_t (&gt)[NT], float (&ld)[NT][KP],
                                                  int (&li)[NT][KP], int row_old, const uint32_t *parity)
 {
     using acc_t = typename Op::acc_t;
@@ -506,7 +531,93 @@ static __device__ __forceinline__ void pipe_step(typename Op::acc_t (&acc_new)[N
     }
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
-        if (any[nt]) tile_insert<Op, KP>(acc_old[nt], thr[nt], gt[nt], ld[nt], li[nt], row_old, h, parity);
+        if (__builtin_expect(any[nt], 0)) tile_insert<Op, KP>(acc_old[nt], thr[nt], gt[nt], ld[nt], li[nt], row_old, h, parity);
+}
+
+// Calls f(std::integral_constant<int, I>) for I = B .. E-1 (a loop whose
+// index must be a compile-time constant in every copy).
+template <int B, int E, class F>
+static __device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+#ifndef LNBNN_GATE_LEAD
+#define LNBNN_GATE_LEAD 2
+#endif
+
+// Registers of one reference tile: A fragments, the seeds in the
+// accumulator layout (four 16-byte LDS reads: no vector instructions, which
+// at the 8-bit rates compete with the MFMAs for issue), row scale.
+template <class Op>
+struct TileRegs {
+    uint4 av[Op::kSteps][Op::kAU];
+    f32x16 sd;
+    int sa;
+};
+
+// Plain LDS loads of one tile.  With the stage copies invisible to the
+// compiler (inline assembly), it schedules these freely: the 4 KB-tile
+// formats load tile t+1 while the MFMAs of tile t run.
+template <class Op>
+static __device__ __forceinline__ void tile_load(const uint4 *frag, const float4 *seed, const int32_t *rsc, int lane,
+                                                 int h, TileRegs<Op> &t)
+{
+#pragma unroll
+    for (int s = 0; s < Op::kSteps; ++s)
+#pragma unroll
+        for (int u = 0; u < Op::kAU; ++u) t.av[s][u] = frag[(s * Op::kAU + u) * 64 + lane];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const float4 sv = seed[2 * g + h];
+        t.sd[4 * g + 0] = sv.x;
+        t.sd[4 * g + 1] = sv.y;
+        t.sd[4 * g + 2] = sv.z;
+        t.sd[4 * g + 3] = sv.w;
+    }
+    t.sa = Op::kScaled ? rsc[lane & 31] : 127;
+}
+
+// One pipeline step on a tile already in registers: its MFMA chain (into
+// acc_new) interleaved with the gate of the previous tile (acc_old); the
+// next tile's LDS loads, issued just before by the caller, lead the block.
+template <class Op, int KP, int NT>
+static __device__ __forceinline__ void pipe_step_regs(typename Op::acc_t (&acc_new)[NT],
+                                                      const typename Op::acc_t (&acc_old)[NT],
+                                                      const uint4 (&bq)[NT][Op::kSteps][Op::kAU],
+                                                      const int (&sb)[NT], const TileRegs<Op> &cur, int h,
+                                                      float (&thr)[NT], typename Op::gate_t (&gt)[NT], float (&ld)[NT][KP],
+                                                      int (&li)[NT][KP], int row_old, const uint32_t *parity)
+{
+    using acc_t = typename Op::acc_t;
+    constexpr int S = Op::kSteps;
+    const acc_t seed_acc = __builtin_bit_cast(acc_t, cur.sd);
+    bool any[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) any[nt] = __builtin_amdgcn_ballot_w64(Op::gate_min(acc_old[nt]) < gt[nt]) != 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+            acc_new[nt] = Op::mma(cur.av[s], bq[nt][s], s == 0 ? seed_acc : acc_new[nt], cur.sa, sb[nt]);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x100, S * Op::kAU + 4 + (Op::kScaled ? 1 : 0), 0);   // next tile's loads
+    // The gate reads the previous tile's accumulators, whose last MFMAs were
+    // issued just before this block: LEAD MFMAs go first so that those
+    // chains have completed when the gate's first vector op issues.
+    constexpr int LEAD = LNBNN_GATE_LEAD < S * NT ? LNBNN_GATE_LEAD : S * NT;
+    __builtin_amdgcn_sched_group_barrier(0x008, LEAD, 0);
+#pragma unroll
+    for (int i = LEAD; i < S * NT; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);     // up to three vector ops
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);     // one MFMA
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+        if (__builtin_expect(any[nt], 0)) tile_insert<Op, KP>(acc_old[nt], thr[nt], gt[nt], ld[nt], li[nt], row_old, h, parity);
 }
 
 template <class Op, int KP, int NT, int MT, int W, int NB>
@@ -521,6 +632,7 @@ void k_dist_topk(DistArgs a)
     constexpr int QB = W * QW;                    // queries per workgroup
     constexpr int PD = NB - 1;                    // stages in flight ahead of the one computed
     constexpr int LPS = StageLoads<Op, MT, W>::total;   // loads per wave per stage
+    constexpr bool kPrefetch = Op::kSteps * Op::kAU == 4;      // 4 KB tiles leave registers for it
     constexpr int RSC = Op::kScaled ? MT * kTileRows : 1;
     static_assert(MT % 2 == 0, "tiles are processed in pairs");
     static_assert(NB >= 2 && (PD - 1) * LPS < 64, "prefetch depth");
@@ -565,7 +677,8 @@ void k_dist_topk(DistArgs a)
 
             float ld[NT][KP];
             int li[NT][KP];
-            float thr[NT], gt[NT];
+            float thr[NT];
+            typename Op::gate_t gt[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int64_t base = ((int64_t)(slice * 2 + h) * a.q_cap + qi[nt]) * KP;
@@ -578,6 +691,11 @@ void k_dist_topk(DistArgs a)
                 thr[nt] = ld[nt][KP - 1];
                 gt[nt] = Op::gate_thr(thr[nt]);
             }
+            // The queries and lists are in registers before any stage copy
+            // is in flight.  (The copies are invisible to the compiler: a
+            // wait it placed later for these loads would be a vmcnt(0) that
+            // drains the prefetches, e.g. on every insertion.)
+            wait_vmcnt<0>();
 
             // Prologue: stages 0..PD-1 in flight, wait for stage 0.  Stages
             // past the end of the chunk are not needed; to keep the vmcnt
@@ -605,6 +723,49 @@ void k_dist_topk(DistArgs a)
                 for (int r = 0; r < 16; ++r) acc1[nt][r] = Op::init();
             int row_prev = 0;
             int buf = 0;
+            if constexpr (kPrefetch) {
+                // 4 KB tiles: tile t+1's LDS loads overlap tile t's MFMAs.
+                // The stage barrier comes before a stage's last tile (whose
+                // loads have completed: lgkmcnt 0), so the next stage's first
+                // tile can be loaded while that last tile computes.
+                TileRegs<Op> tr[2];           // tile m lives in tr[m % 2]
+                tile_load<Op>(s_frag[0], s_seed[0], s_rsc[0], lane, h, tr[0]);
+                for (int st = 0; st < n_st; ++st) {
+                    {   // stage st + PD goes into the buffer stage st - 1 used
+                        const int sn = st + PD;
+                        const int64_t ts = t0 + (int64_t)(sn < n_st ? sn : 0) * MT;
+                        const int nb = (buf + PD) % NB;
+                        stage_copy<Op, MT, W, TILE_U4>(a.frag + ts * TILE_U4, s_frag[nb], a.seed + ts * kTileRows,
+                                                       reinterpret_cast<float *>(s_seed[nb]),
+                                                       a.row_scale + ts * kTileRows, s_rsc[nb], wave, lane);
+                    }
+                    static_for<0, MT>([&](auto M) {
+                        constexpr int m = decltype(M)::value;
+                        const int row_t = (int)((t0 + (int64_t)st * MT + m) * kTileRows) + 4 * h;
+                        if constexpr (m == MT - 1) {
+                            wait_vmcnt<(PD - 1) * LPS>();       // stage st + 1 landed (this wave's part)
+                            __builtin_amdgcn_s_waitcnt(0xc07f); // lgkmcnt(0): this wave's reads of stage st done
+                            asm volatile("" ::: "memory");
+                            __builtin_amdgcn_s_barrier();
+                            asm volatile("" ::: "memory");
+                            const int nb = (buf + 1) % NB;
+                            tile_load<Op>(s_frag[nb], s_seed[nb], s_rsc[nb], lane, h, tr[(m + 1) % 2]);
+                        } else {
+                            tile_load<Op>(s_frag[buf] + (m + 1) * TILE_U4, s_seed[buf] + (m + 1) * 8,
+                                          s_rsc[buf] + (Op::kScaled ? (m + 1) * kTileRows : 0), lane, h,
+                                          tr[(m + 1) % 2]);
+                        }
+                        if constexpr (m % 2 == 0)
+                            pipe_step_regs<Op, KP, NT>(acc0, acc1, bq, sb, tr[0], h, thr, gt, ld, li, row_prev,
+                                                       a.parity);
+                        else
+                            pipe_step_regs<Op, KP, NT>(acc1, acc0, bq, sb, tr[1], h, thr, gt, ld, li, row_prev,
+                                                       a.parity);
+                        row_prev = row_t;
+                    });
+                    buf = (buf + 1) % NB;
+                }
+            } else
             for (int st = 0; st < n_st; ++st) {
                 {   // stage st + PD goes into the buffer stage st - 1 used
                     const int sn = st + PD;
