@@ -346,14 +346,41 @@ def serving_leg(args, L, torch, np, synth, ix_exact, ix_fp8, mu_exact_qps, mu_fp
     return out
 
 
+def class_sweep_leg(args, L, torch, np, synth):
+    """Exact path as the number of classes grows at a fixed 30 x 2000
+    references per class (64 query images of the same size mix per point):
+    the shape of the paper's class-count experiment (Fig. 5).  Exact search
+    is linear in the number of references; the paper's approximate index
+    grows with its logarithm."""
+    base = synth.CONFIGS["L"]
+    rows = []
+    for nc in (2, 8, 32, 128, 256):
+        cfg = synth.scaled(base, n_classes=nc, n_img=64)
+        R, labels = synth.gen_index(cfg)
+        Q, off, true_cls = synth.gen_queries(cfg)
+        ix = L.lnbnn_build_index(R, labels, nc, L.LNBNN_MODE_BIT(L.LNBNN_EXACT_I8))
+        del R
+        dq = torch.from_numpy(Q).cuda()
+        dt, k1, _, cls = time_exact(args, L, torch, np, ix, dq, off, nc, L.LNBNN_EXACT_I8, 2, 1)
+        ix.free()
+        n_q = int(Q.shape[0])
+        rows.append({"n_classes": nc, "n_refs": cfg.n_refs, "query_desc": n_q,
+                     "query_desc_per_s": n_q / dt, "ms_per_image": dt * 1e3 / 64,
+                     "dist_kernel_ms": k1,
+                     "dist_kernel_ops_per_s": 2.0 * 128 * cfg.n_refs * n_q / (k1 / 1e3),
+                     "accuracy_statistic": float(np.mean(cls == true_cls))})
+        log(f"class sweep: {rows[-1]}")
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--k", type=int, default=10)
-    ap.add_argument("--legs", default="exact,fp8,serving",
-                    help="comma list: exact (always), fp8, serving")
+    ap.add_argument("--legs", default="exact,fp8,serving,sweep",
+                    help="comma list: exact (always), fp8, serving, sweep")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -391,9 +418,17 @@ def main():
             res["p99_image_ms"] = res["serving"]["rho_0.7"]["batched_exact"]["p99_ms"]
         except Exception as e:
             res["serving"] = {"error": repr(e)}
-    if ix8 is not None:
-        ix8.free()
-    ix.free()
+    for x in (ix8, ix):
+        try:
+            if x is not None:
+                x.free()                  # frees the HBM for the sweep's indexes
+        except Exception as e:
+            log(f"index free: {e!r}")
+    if "sweep" in legs:
+        try:
+            res["class_sweep"] = class_sweep_leg(args, L, torch, np, synth)
+        except Exception as e:
+            res["class_sweep"] = {"error": repr(e)}
     print(json.dumps(res))
 
 

@@ -633,12 +633,33 @@ void k_dist_topk(DistArgs a)
     constexpr int PD = NB - 1;                    // stages in flight ahead of the one computed
     constexpr int LPS = StageLoads<Op, MT, W>::total;   // loads per wave per stage
     constexpr bool kPrefetch = Op::kSteps * Op::kAU == 4;      // 4 KB tiles leave registers for it
+    // With 3+ buffers the 4 KB-tile path synchronises per buffer instead of
+    // per stage: PF = NB - 2 stages in flight leave one stage of slack, so a
+    // wave that inserts delays only itself.
+    constexpr bool kCounters = kPrefetch && NB >= 3;
+    constexpr int PF = kCounters ? NB - 2 : PD;
     constexpr int RSC = Op::kScaled ? MT * kTileRows : 1;
     static_assert(MT % 2 == 0, "tiles are processed in pairs");
     static_assert(NB >= 2 && (PD - 1) * LPS < 64, "prefetch depth");
     __shared__ uint4 s_frag[NB][STAGE_U4];
     __shared__ float4 s_seed[NB][MT * 8];
     __shared__ int32_t s_rsc[NB][RSC];
+    // [0, NB): waves whose share of the buffer's current stage has landed;
+    // [NB, 2NB): waves done reading it (counts accumulate over the item)
+    __shared__ uint32_t s_cnt[2 * NB];
+    auto cnt_signal = [&](int i) {
+        asm volatile("" ::: "memory");
+        if ((threadIdx.x & 63) == 0)
+            __hip_atomic_fetch_add(&s_cnt[i], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    auto cnt_wait = [&](int i, uint32_t target) {
+        // bounded: a wrong count could only give wrong results, never a hang
+        for (int it = 0; it < (1 << 20); ++it) {
+            if (__hip_atomic_load(&s_cnt[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= target) break;
+            __builtin_amdgcn_s_sleep(1);
+        }
+        asm volatile("" ::: "memory");
+    };
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -702,15 +723,24 @@ void k_dist_topk(DistArgs a)
             // arithmetic uniform they re-load the chunk's first stage into a
             // buffer that is never read.
             const int n_st = n_t / MT;
+            if constexpr (kCounters) {
+                if (tid < 2 * NB) s_cnt[tid] = 0u;
+                __syncthreads();
+            }
 #pragma unroll
-            for (int p = 0; p < PD; ++p) {
+            for (int p = 0; p < PF; ++p) {
                 const int64_t ts = t0 + (int64_t)(p < n_st ? p : 0) * MT;
                 stage_copy<Op, MT, W, TILE_U4>(a.frag + ts * TILE_U4, s_frag[p], a.seed + ts * kTileRows,
                                                reinterpret_cast<float *>(s_seed[p]), a.row_scale + ts * kTileRows,
                                                s_rsc[p], wave, lane);
             }
-            wait_vmcnt<(PD - 1) * LPS>();
-            __syncthreads();
+            wait_vmcnt<(PF - 1) * LPS>();
+            if constexpr (kCounters) {
+                cnt_signal(0);                  // this wave's share of stage 0 has landed
+                cnt_wait(0, W);
+            } else {
+                __syncthreads();
+            }
 
             // Software pipeline over pairs of tiles: the MFMA chain of one
             // tile is issued in the same block as the gate of the previous
@@ -723,7 +753,52 @@ void k_dist_topk(DistArgs a)
                 for (int r = 0; r < 16; ++r) acc1[nt][r] = Op::init();
             int row_prev = 0;
             int buf = 0;
-            if constexpr (kPrefetch) {
+            if constexpr (kCounters) {
+                // Stage s lives in buffer s % NB as that buffer's fill s / NB.
+                // Before refilling a buffer a wave waits until every wave has
+                // finished reading its previous fill (s_cnt[NB + b]); before
+                // reading a stage it waits until every wave's share has landed
+                // (s_cnt[b]).  Each wave signals "landed" for stage s + 1 at
+                // the start of stage s (its copy was issued a stage earlier)
+                // and "read" for stage s once its last tile is in registers.
+                TileRegs<Op> tr[2];           // tile m lives in tr[m % 2]
+                tile_load<Op>(s_frag[0], s_seed[0], s_rsc[0], lane, h, tr[0]);
+                for (int st = 0; st < n_st; ++st) {
+                    {
+                        const int sn = st + PF;
+                        const int nb = sn % NB;
+                        cnt_wait(NB + nb, (uint32_t)(W * (sn / NB)));
+                        const int64_t ts = t0 + (int64_t)(sn < n_st ? sn : 0) * MT;
+                        stage_copy<Op, MT, W, TILE_U4>(a.frag + ts * TILE_U4, s_frag[nb], a.seed + ts * kTileRows,
+                                                       reinterpret_cast<float *>(s_seed[nb]),
+                                                       a.row_scale + ts * kTileRows, s_rsc[nb], wave, lane);
+                        wait_vmcnt<(PF - 1) * LPS>();   // this wave's share of stage st + 1 landed
+                        cnt_signal((st + 1) % NB);
+                    }
+                    static_for<0, MT>([&](auto M) {
+                        constexpr int m = decltype(M)::value;
+                        const int row_t = (int)((t0 + (int64_t)st * MT + m) * kTileRows) + 4 * h;
+                        if constexpr (m == MT - 1) {
+                            __builtin_amdgcn_s_waitcnt(0xc07f); // lgkmcnt(0): this wave's reads of stage st done
+                            cnt_signal(NB + st % NB);
+                            const int nb = (st + 1) % NB;
+                            cnt_wait(nb, (uint32_t)(W * ((st + 1) / NB + 1)));
+                            tile_load<Op>(s_frag[nb], s_seed[nb], s_rsc[nb], lane, h, tr[(m + 1) % 2]);
+                        } else {
+                            tile_load<Op>(s_frag[st % NB] + (m + 1) * TILE_U4, s_seed[st % NB] + (m + 1) * 8,
+                                          s_rsc[st % NB] + (Op::kScaled ? (m + 1) * kTileRows : 0), lane, h,
+                                          tr[(m + 1) % 2]);
+                        }
+                        if constexpr (m % 2 == 0)
+                            pipe_step_regs<Op, KP, NT>(acc0, acc1, bq, sb, tr[0], h, thr, gt, ld, li, row_prev,
+                                                       a.parity);
+                        else
+                            pipe_step_regs<Op, KP, NT>(acc1, acc0, bq, sb, tr[1], h, thr, gt, ld, li, row_prev,
+                                                       a.parity);
+                        row_prev = row_t;
+                    });
+                }
+            } else if constexpr (kPrefetch) {
                 // 4 KB tiles: tile t+1's LDS loads overlap tile t's MFMAs.
                 // The stage barrier comes before a stage's last tile (whose
                 // loads have completed: lgkmcnt 0), so the next stage's first

@@ -113,6 +113,32 @@ def test_full_exact_sampled_against_oracle(big):
     assert np.array_equal(tot[m], wt[0]) and cls[m] == wc[0]
 
 
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("k", [5, 20])
+def test_full_exact_other_k_sampled(big, k):
+    """The other neighbourhood sizes of the large configuration: 64 sampled
+    descriptors' lists and one whole image's totals, in the batched launch."""
+    import torch
+    cfg, R, labels, Q, off, ix, _ = big
+    dq = torch.from_numpy(Q).cuda()
+    _say(f"classifying 512 images at k={k}")
+    cls, tot, ni, nd = L.lnbnn_classify(ix, dq, off, k, L.LNBNN_EXACT_I8, want_neighbours=True)
+    torch.cuda.synchronize()
+    cls, tot, ni, nd = cls.cpu().numpy(), tot.cpu().numpy(), ni.cpu().numpy(), nd.cpu().numpy()
+    assert _sorted_lists(ni, nd)
+    T = _totals_from_lists(ni, nd, labels, cfg.n_classes, off, k)
+    assert np.array_equal(T, tot) and np.array_equal(np.argmin(tot, axis=1), cls)
+    imgs = [7, 300]
+    sel = np.concatenate([np.arange(off[m], off[m] + 32) for m in imgs])
+    wi, wd = oracle.knn_expanded(Q[sel], R, k + 1)
+    assert np.array_equal(ni[sel], wi) and np.array_equal(nd[sel].astype(np.int64), wd)
+    m = int(np.argmin(np.diff(off)))
+    s, e = int(off[m]), int(off[m + 1])
+    _say(f"oracle classification of image {m} at k={k}")
+    wt, wc, _, _ = oracle.classify(Q[s:e], R, labels, cfg.n_classes, np.array([0, e - s]), k)
+    assert np.array_equal(tot[m], wt[0]) and cls[m] == wc[0]
+
+
 @pytest.fixture(scope="module")
 def bigf():
     import torch
