@@ -76,6 +76,10 @@ struct FloatKeys {
     static constexpr bool kParity = false;
     static __device__ __forceinline__ float init() { return __builtin_inff(); }
     static __device__ __forceinline__ float gate_min(const f32x16 &acc) { return min16(acc); }
+    static __device__ __forceinline__ float group_min(const f32x16 &a, int g)
+    {
+        return __builtin_fminf(__builtin_fminf(__builtin_fminf(a[4 * g], a[4 * g + 1]), a[4 * g + 2]), a[4 * g + 3]);
+    }
     static __device__ __forceinline__ float gate_thr(float thr) { return thr; }
     static __device__ __forceinline__ float key(const f32x16 &acc, int r, uint32_t, int) { return acc[r]; }
 };
@@ -208,6 +212,10 @@ struct OpI8 {
     static constexpr int kPadSeed = 1 << 30;
     static __device__ __forceinline__ int init() { return 0x7fffffff; }
     static __device__ __forceinline__ int gate_min(const i32x16 &acc) { return min16(acc); }
+    static __device__ __forceinline__ int group_min(const i32x16 &a, int g)
+    {
+        return min(min(min(a[4 * g], a[4 * g + 1]), a[4 * g + 2]), a[4 * g + 3]);
+    }
     // key = 2D + b < thr implies D < ceil(thr / 2); no bound while the list
     // is not full (thr = +inf)
     static __device__ __forceinline__ int gate_thr(float thr)
@@ -306,12 +314,19 @@ static __device__ __forceinline__ void tile_insert(const typename Op::acc_t &acc
     // this (rarely taken) path instead of being hoisted into the gate
     int base = row0;
     asm volatile("" : "+v"(base));
+    // registers 4g..4g+3 hold rows 8g + 4h + 0..3: only the groups whose
+    // minimum passes the gate are walked (usually one)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const float v = Op::key(acc, r, pm, h);
-        const bool take = v < thr;
-        if (__builtin_amdgcn_ballot_w64(take) != 0) {
-            if (take) list_insert<KP>(v, base + 8 * (r >> 2) + (r & 3), ld, li, thr);
+    for (int g = 0; g < 4; ++g) {
+        if (__builtin_amdgcn_ballot_w64(Op::group_min(acc, g) < gt) == 0) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 4 * g + i;
+            const float v = Op::key(acc, r, pm, h);
+            const bool take = v < thr;
+            if (__builtin_amdgcn_ballot_w64(take) != 0) {
+                if (take) list_insert<KP>(v, base + 8 * g + i, ld, li, thr);
+            }
         }
     }
     gt = Op::gate_thr(thr);
@@ -332,8 +347,6 @@ static __device__ __forceinline__ void tiles_select(const typename Op::acc_t (&a
         if (__builtin_expect(any[nt], 0)) tile_insert<Op, KP>(acc[nt], thr[nt], gt[nt], ld[nt], li[nt], row0, h, parity);
 }
 
-typedef __attribute__((address_space(1))) const void *gmem_ptr;
-typedef __attribute__((address_space(3))) void *lds_ptr;
 
 // Asynchronous copy of one LDS stage (MT tiles of fragments, their seeds
 // and, for scaled formats, their row scales) straight from global memory into
@@ -718,10 +731,10 @@ void k_dist_topk(DistArgs a)
             // drains the prefetches, e.g. on every insertion.)
             wait_vmcnt<0>();
 
-            // Prologue: stages 0..PD-1 in flight, wait for stage 0.  Stages
-            // past the end of the chunk are not needed; to keep the vmcnt
-            // arithmetic uniform they re-load the chunk's first stage into a
-            // buffer that is never read.
+            // Prologue: the first PF stages in flight, wait for stage 0.
+            // Stages past the end of the chunk are not needed; to keep the
+            // vmcnt arithmetic uniform they re-load the chunk's first stage
+            // (whose values are never used).
             const int n_st = n_t / MT;
             if constexpr (kCounters) {
                 if (tid < 2 * NB) s_cnt[tid] = 0u;
