@@ -59,7 +59,7 @@ enum { LNBNN_U8 = 0, LNBNN_F32 = 1 };
 enum {
     LNBNN_EXACT_F16 = 0,   /* u8 data, FP16 matrix cores, FP32 accumulate: exact */
     LNBNN_EXACT_BF16 = 1,  /* u8 data, BF16 matrix cores, FP32 accumulate: exact */
-    LNBNN_FP8_RERANK = 2,  /* f32 data: FP8 e4m3 candidate pass, exact FP32 re-rank of 4k
+    LNBNN_FP8_RERANK = 2,  /* f32 data: FP8 e4m3 candidate pass, exact FP32 re-rank of 4k <= 128
                               candidates (the best 4k FP8 keys of the union of per-row-half
                               lists of >= 2k keys each; the FP8 top 2k are always among them) */
     LNBNN_EXACT_I8 = 3     /* u8 data shifted by -128, INT8 matrix cores, INT32 accumulate: exact

@@ -187,7 +187,7 @@ static int blocks_per_cu(lnbnn_index *ix, int v, int fmt, int kpb)
 
 static int default_variant(int fmt, int kp)
 {
-    if (fmt == FMT_FP8) return variant_supports(4, fmt, kp) ? 4 : 6;
+    if (fmt == FMT_FP8) return variant_supports(4, fmt, kp) ? 4 : variant_supports(6, fmt, kp) ? 6 : 0;
     // 8 waves x 64 queries share each LDS stage (half the reference traffic
     // of 4-wave workgroups); 32 queries per wave where the longer neighbour
     // lists need the registers.

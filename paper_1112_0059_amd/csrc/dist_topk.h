@@ -634,7 +634,10 @@ static __device__ __forceinline__ void pipe_step_regs(typename Op::acc_t (&acc_n
 }
 
 template <class Op, int KP, int NT, int MT, int W, int NB>
-__global__ __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W), amdgpu_waves_per_eu(2, 2)))
+// Two waves per SIMD (256 registers each), except the 64-entry lists, which
+// need one wave per SIMD (W = 4) and its full register file.
+__global__ __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W),
+                          amdgpu_waves_per_eu(KP > 40 ? 1 : 2, KP > 40 ? 1 : 2)))
 void k_dist_topk(DistArgs a)
 {
     constexpr int S = Op::kSteps;
@@ -915,8 +918,9 @@ static void *pick_variant(int v)
 {
     switch (v) {
     case 0: return kernel_ptr<Op, KP, 1, 2, 4, 4>();
-    case 6: return kernel_ptr<Op, KP, 1, 4, 8, 4>();
     }
+    if constexpr (KP <= 40)
+        if (v == 6) return kernel_ptr<Op, KP, 1, 4, 8, 4>();
     if constexpr (Op::kFmt == FMT_FP8) {
         if constexpr (KP <= 20) {
             switch (v) {

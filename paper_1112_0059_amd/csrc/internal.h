@@ -11,7 +11,7 @@ constexpr int kDim = 128;
 constexpr int kTileRows = 32;            // rows of one MFMA A tile
 constexpr int kPadRows = 256;            // index rows are padded to this multiple
 constexpr int kMaxKP = 33;               // k + 1 <= 33
-constexpr int kMaxFp8K = 16;             // FP8 mode re-ranks 4k <= 64 candidates
+constexpr int kMaxFp8K = 32;             // FP8 mode re-ranks 4k <= 128 candidates
 
 // Element formats of the packed reference tiles.
 enum Fmt { FMT_F16 = 0, FMT_BF16 = 1, FMT_FP8 = 2, FMT_I8 = 3 };
@@ -124,7 +124,8 @@ int kp_bucket(int kp, int fmt);         // list length compiled for kp (0 = unsu
     X(fp8, OpFP8, FMT_FP8, 4)     \
     X(fp8, OpFP8, FMT_FP8, 8)     \
     X(fp8, OpFP8, FMT_FP8, 20)    \
-    X(fp8, OpFP8, FMT_FP8, 40)
+    X(fp8, OpFP8, FMT_FP8, 40)    \
+    X(fp8, OpFP8, FMT_FP8, 64)
 
 // Upload-side packing.  refs_u8 / refs_f32 are device pointers.
 hipError_t launch_pack_u8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, int fmt,

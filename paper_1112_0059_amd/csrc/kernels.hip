@@ -247,7 +247,7 @@ int kp_bucket(int kp, int fmt)
         for (int x : b)
             if (kp <= x) return x;
     } else if (fmt == FMT_FP8) {
-        static const int b[] = {4, 8, 20, 40};   // per-half candidate lists (>= 2k)
+        static const int b[] = {4, 8, 20, 40, 64};   // per-half candidate lists (>= 2k)
         for (int x : b)
             if (kp <= x) return x;
     }
@@ -261,6 +261,8 @@ bool variant_supports(int v, int fmt, int kp)
     if (b == 0) return false;
     // the deep stage variants need the 4 KB tiles of the 8-bit formats
     if ((v == 8 || v == 9) && (fmt == FMT_F16 || fmt == FMT_BF16)) return false;
+    // 64-entry lists take a SIMD's whole register file: one wave per SIMD
+    if (fmt == FMT_FP8 && b > 40) return v == 0;
     if (fmt == FMT_FP8) return v == 0 || v == 6 || ((v == 1 || v == 4 || v == 5 || v >= 8) && b <= 20);
     return kVariants[v].nt == 1 || b <= 16;
 }

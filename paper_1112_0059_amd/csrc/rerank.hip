@@ -160,66 +160,86 @@ __global__ __launch_bounds__(256) void k_cand_merge(RerankArgs a)
     }
 }
 
-// One wave per query.  Lane j < n_cand computes the candidate's squared
-// distance in FP32, directly as sum_t (q_t - r_t)^2 in dimension order; the
-// candidates are ranked by (distance, index); the k+1 smallest are the
-// neighbours.  The lane of rank j < k emits Algorithm 2's update for its
-// class if no lower rank has that class: dist_C - dist_B, formed in FP64
-// from the two FP32 distances (exactly).
+// One wave per query.  Lane j holds candidates j and j + 64 (n_cand <= 128)
+// and computes each one's squared distance in FP32, directly as
+// sum_t (q_t - r_t)^2 in dimension order; the candidates are ranked by
+// (distance, index); the k+1 smallest are the neighbours.  The holder of
+// rank j < k emits Algorithm 2's update for its class if no lower rank has
+// that class: dist_C - dist_B, formed in FP64 from the two FP32 distances
+// (exactly).
 __global__ __launch_bounds__(256) void k_rerank(RerankArgs a)
 {
     const int lane = threadIdx.x & 63;
     const int64_t n_q = a.bd->n_q;
     const int k = a.k;
+    const int nc = a.n_cand > 64 ? 2 : 1;       // candidate slots per lane
     for (int64_t q = blockIdx.x * 4 + (threadIdx.x >> 6); q < n_q; q += (int64_t)gridDim.x * 4) {
-        float d = __builtin_inff();
-        int idx = 0x7fffffff;
-        if (lane < a.n_cand) {
-            idx = a.cand[q * a.n_cand + lane];
-            if (idx >= 0 && idx < a.n_refs) {
-                const float4 *qr = reinterpret_cast<const float4 *>(a.qf32 + q * kDim);
-                const float4 *rr = reinterpret_cast<const float4 *>(a.ref_f32 + (int64_t)idx * kDim);
-                float s = 0.0f;
-                for (int c = 0; c < kDim / 4; ++c) {
-                    const float4 x = qr[c], y = rr[c];
-                    float t = x.x - y.x;
-                    s = fmaf(t, t, s);
-                    t = x.y - y.y;
-                    s = fmaf(t, t, s);
-                    t = x.z - y.z;
-                    s = fmaf(t, t, s);
-                    t = x.w - y.w;
-                    s = fmaf(t, t, s);
-                }
-                d = s;
-            } else {
-                idx = 0x7fffffff;
+        float d[2];
+        int idx[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int j = lane + 64 * c;
+            d[c] = __builtin_inff();
+            idx[c] = 0x7fffffff;
+            if (j >= a.n_cand) continue;
+            const int r = a.cand[q * a.n_cand + j];
+            if (r < 0 || r >= a.n_refs) continue;
+            const float4 *qr = reinterpret_cast<const float4 *>(a.qf32 + q * kDim);
+            const float4 *rr = reinterpret_cast<const float4 *>(a.ref_f32 + (int64_t)r * kDim);
+            float s = 0.0f;
+            for (int t = 0; t < kDim / 4; ++t) {
+                const float4 x = qr[t], y = rr[t];
+                float e = x.x - y.x;
+                s = fmaf(e, e, s);
+                e = x.y - y.y;
+                s = fmaf(e, e, s);
+                e = x.z - y.z;
+                s = fmaf(e, e, s);
+                e = x.w - y.w;
+                s = fmaf(e, e, s);
+            }
+            d[c] = s;
+            idx[c] = r;
+        }
+        int rank[2] = {0, 0};
+        for (int c2 = 0; c2 < nc; ++c2) {
+            for (int i = 0; i < 64; ++i) {
+                const float di = __shfl(d[c2], i);
+                const int ii = __shfl(idx[c2], i);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) rank[c] += pair_less(di, ii, d[c], idx[c]) ? 1 : 0;
             }
         }
-        int rank = 0;
-        for (int i = 0; i < 64; ++i) {
-            const float di = __shfl(d, i);
-            const int ii = __shfl(idx, i);
-            rank += pair_less(di, ii, d, idx) ? 1 : 0;
+        const unsigned long long m0 = __builtin_amdgcn_ballot_w64(rank[0] == k);
+        const unsigned long long m1 = __builtin_amdgcn_ballot_w64(nc > 1 && rank[1] == k);
+        const float db = m0 ? __shfl(d[0], (int)__builtin_ctzll(m0)) : __shfl(d[1], (int)__builtin_ctzll(m1));
+        int cls[2];
+        bool first[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            first[c] = c < nc && rank[c] < k;
+            cls[c] = first[c] ? a.labels[idx[c]] : -1;
         }
-        const unsigned long long mb = __builtin_amdgcn_ballot_w64(rank == k);
-        const int src = (int)__builtin_ctzll(mb);
-        const float db = __shfl(d, src);
-        int cls = -1;
-        if (rank < k) cls = a.labels[idx];
-        bool first = rank < k;
-        for (int i = 0; i < 64; ++i) {
-            const int ri = __shfl(rank, i);
-            const int ci = __shfl(cls, i);
-            if (ri < rank && ci == cls) first = false;
+        for (int c2 = 0; c2 < nc; ++c2) {
+            for (int i = 0; i < 64; ++i) {
+                const int ri = __shfl(rank[c2], i);
+                const int ci = __shfl(cls[c2], i);
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    if (ri < rank[c] && ci == cls[c]) first[c] = false;
+            }
         }
-        if (rank < k) {
-            a.upd_cls[q * k + rank] = first ? cls : -1;
-            a.upd_delta[q * k + rank] = (double)d - (double)db;
-        }
-        if (a.nbr_idx && rank <= k) {
-            a.nbr_idx[q * (k + 1) + rank] = idx;
-            a.nbr_dist[q * (k + 1) + rank] = d;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            if (c >= nc) break;
+            if (rank[c] < k) {
+                a.upd_cls[q * k + rank[c]] = first[c] ? cls[c] : -1;
+                a.upd_delta[q * k + rank[c]] = (double)d[c] - (double)db;
+            }
+            if (a.nbr_idx && rank[c] <= k) {
+                a.nbr_idx[q * (k + 1) + rank[c]] = idx[c];
+                a.nbr_dist[q * (k + 1) + rank[c]] = d[c];
+            }
         }
     }
 }

@@ -84,12 +84,12 @@ def _compare(got, want, labels, off, k, n_classes, min_recall=0.995):
 def small():
     cfg, R, labels, Q, off, true_cls = _problem()
     ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(FP8))
-    want = {k: oracle.classify(Q, R, labels, cfg.n_classes, off, k) for k in (1, 5, 10)}
+    want = {k: oracle.classify(Q, R, labels, cfg.n_classes, off, k) for k in (1, 5, 10, 20, 32)}
     yield cfg, R, labels, Q, off, ix, want
     ix.free()
 
 
-@pytest.mark.parametrize("k", [1, 5, 10])
+@pytest.mark.parametrize("k", [1, 5, 10, 20, 32])
 def test_fp8_small_quality(small, k):
     cfg, R, labels, Q, off, ix, want = small
     _say(f"fp8 small k={k}")
@@ -168,7 +168,7 @@ def test_fp8_edge_cases():
     Unstructured random vectors are nearly equidistant, the hardest case for
     an FP8 shortlist, so recall is only bounded loosely there."""
     rng = np.random.default_rng(3)
-    for n_refs, k, min_recall in ((1000 + 7, 10, 0.95), (40, 10, 1.0), (12, 3, 1.0)):
+    for n_refs, k, min_recall in ((1000 + 7, 10, 0.95), (40, 10, 1.0), (12, 3, 1.0), (128, 32, 1.0), (100, 25, 1.0)):
         R = np.maximum(rng.standard_normal((n_refs, 128)), 0).astype(np.float32)
         R[::17] = 0.0
         labels = rng.integers(0, 5, size=n_refs).astype(np.int32)
@@ -194,7 +194,9 @@ def test_fp8_rejects():
     ix = L.lnbnn_build_index(R, lab, 1, L.LNBNN_MODE_BIT(FP8))
     try:
         with pytest.raises(L.LnbnnError):
-            L.lnbnn_classify(ix, R[:3], np.array([0, 3], np.int64), 17, FP8)      # k > 16
+            L.lnbnn_classify(ix, R[:3], np.array([0, 3], np.int64), 33, FP8)      # k > 32
+        with pytest.raises(L.LnbnnError):
+            L.lnbnn_classify(ix, R[:3], np.array([0, 3], np.int64), 26, FP8)      # 4k > n_refs
         with pytest.raises(L.LnbnnError):
             L.lnbnn_classify(ix, R[:3], np.array([0, 3], np.int64), 5, L.LNBNN_EXACT_F16)
         with pytest.raises(L.LnbnnError):
