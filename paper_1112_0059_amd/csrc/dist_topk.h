@@ -561,6 +561,12 @@ static __device__ __forceinline__ void static_for(F &&f)
 #ifndef LNBNN_GATE_LEAD
 #define LNBNN_GATE_LEAD 2
 #endif
+#ifndef LNBNN_READS_AFTER_LEAD
+#define LNBNN_READS_AFTER_LEAD 1
+#endif
+#ifndef LNBNN_LANDED_AT
+#define LNBNN_LANDED_AT (-1)        // -1: the middle of the stage
+#endif
 
 // Registers of one reference tile: A fragments, the seeds in the
 // accumulator layout (four 16-byte LDS reads: no vector instructions, which
@@ -617,12 +623,18 @@ static __device__ __forceinline__ void pipe_step_regs(typename Op::acc_t (&acc_n
         for (int nt = 0; nt < NT; ++nt)
             acc_new[nt] = Op::mma(cur.av[s], bq[nt][s], s == 0 ? seed_acc : acc_new[nt], cur.sa, sb[nt]);
     }
-    __builtin_amdgcn_sched_group_barrier(0x100, S * Op::kAU + 4 + (Op::kScaled ? 1 : 0), 0);   // next tile's loads
     // The gate reads the previous tile's accumulators, whose last MFMAs were
     // issued just before this block: LEAD MFMAs go first so that those
     // chains have completed when the gate's first vector op issues.
     constexpr int LEAD = LNBNN_GATE_LEAD < S * NT ? LNBNN_GATE_LEAD : S * NT;
+    constexpr int NREAD = S * Op::kAU + 4 + (Op::kScaled ? 1 : 0);   // next tile's LDS loads
+#if LNBNN_READS_AFTER_LEAD
     __builtin_amdgcn_sched_group_barrier(0x008, LEAD, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, NREAD, 0);
+#else
+    __builtin_amdgcn_sched_group_barrier(0x100, NREAD, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, LEAD, 0);
+#endif
 #pragma unroll
     for (int i = LEAD; i < S * NT; ++i) {
         __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);     // up to three vector ops
@@ -654,6 +666,11 @@ void k_dist_topk(DistArgs a)
     // wave that inserts delays only itself.
     constexpr bool kCounters = kPrefetch && NB >= 3;
     constexpr int PF = kCounters ? NB - 2 : PD;
+    // Tile of stage s at which a wave confirms and announces that its copies
+    // of stage s + 1 have landed: later leaves the copies more time, earlier
+    // leaves the other waves more slack.  The middle measured best.
+    constexpr int kLandedAt = LNBNN_LANDED_AT >= 0 && LNBNN_LANDED_AT < MT - 1 ? LNBNN_LANDED_AT
+                              : (MT / 2 < MT - 2 ? MT / 2 : MT - 2);
     constexpr int RSC = Op::kScaled ? MT * kTileRows : 1;
     static_assert(MT % 2 == 0, "tiles are processed in pairs");
     static_assert(NB >= 2 && (PD - 1) * LPS < 64, "prefetch depth");
@@ -774,9 +791,10 @@ void k_dist_topk(DistArgs a)
                 // Before refilling a buffer a wave waits until every wave has
                 // finished reading its previous fill (s_cnt[NB + b]); before
                 // reading a stage it waits until every wave's share has landed
-                // (s_cnt[b]).  Each wave signals "landed" for stage s + 1 at
-                // the start of stage s (its copy was issued a stage earlier)
-                // and "read" for stage s once its last tile is in registers.
+                // (s_cnt[b]).  Each wave signals "landed" for stage s + 1 in
+                // the middle of stage s (its copy was issued at the start of
+                // stage s + 1 - PF) and "read" for stage s once its last tile
+                // is in registers.
                 TileRegs<Op> tr[2];           // tile m lives in tr[m % 2]
                 tile_load<Op>(s_frag[0], s_seed[0], s_rsc[0], lane, h, tr[0]);
                 for (int st = 0; st < n_st; ++st) {
@@ -788,12 +806,14 @@ void k_dist_topk(DistArgs a)
                         stage_copy<Op, MT, W, TILE_U4>(a.frag + ts * TILE_U4, s_frag[nb], a.seed + ts * kTileRows,
                                                        reinterpret_cast<float *>(s_seed[nb]),
                                                        a.row_scale + ts * kTileRows, s_rsc[nb], wave, lane);
-                        wait_vmcnt<(PF - 1) * LPS>();   // this wave's share of stage st + 1 landed
-                        cnt_signal((st + 1) % NB);
                     }
                     static_for<0, MT>([&](auto M) {
                         constexpr int m = decltype(M)::value;
                         const int row_t = (int)((t0 + (int64_t)st * MT + m) * kTileRows) + 4 * h;
+                        if constexpr (m == kLandedAt) {
+                            wait_vmcnt<(PF - 1) * LPS>();   // this wave's share of stage st + 1 landed
+                            cnt_signal((st + 1) % NB);
+                        }
                         if constexpr (m == MT - 1) {
                             __builtin_amdgcn_s_waitcnt(0xc07f); // lgkmcnt(0): this wave's reads of stage st done
                             cnt_signal(NB + st % NB);
