@@ -16,7 +16,13 @@
  *     exception crosses this boundary; lnbnn_last_error() gives a message
  *     for the calling thread's last failure;
  *   - descriptors are row-major [n, dim] with dim == LNBNN_DIM (128, the
- *     SIFT dimension the paper uses, Sec. 6);
+ *     SIFT dimension the paper uses, Sec. 6), or LNBNN_DIM_LOC (160) for
+ *     location-augmented u8 descriptors (the paper weights a descriptor's
+ *     image location by alpha = 1.6, Sec. 6): the library takes all 160
+ *     bytes as one vector; how the location is coded into bytes 128..159
+ *     is the caller's choice (one exact-integer coding: 16 copies each of
+ *     the two coordinate codes, so that 16 (dx^2 + dy^2) carries the
+ *     weight);
  *   - distances are squared Euclidean (no square root);
  *   - nearest neighbours are ordered by (distance, reference index): equal
  *     distances go to the lower index; argmin ties go to the lower class;
@@ -37,6 +43,7 @@ extern "C" {
 #endif
 
 #define LNBNN_DIM 128
+#define LNBNN_DIM_LOC 160       /* location-augmented u8 descriptors: INT8 mode only */
 #define LNBNN_MAX_K 32          /* k <= 32, so at most 33 neighbours */
 
 typedef struct lnbnn_index lnbnn_index;   /* opaque, library-owned */
@@ -82,6 +89,8 @@ enum {
  * the class lookup Class(p), Sec. 6.1's per-descriptor "accessory data").
  *
  *   refs       [n_refs, dim] LNBNN_U8 (values 0..255) or LNBNN_F32
+ *   dim        LNBNN_DIM, or LNBNN_DIM_LOC with U8 data and mode_mask =
+ *              LNBNN_MODE_BIT(LNBNN_EXACT_I8) (queries then carry 160 bytes)
  *   labels     [n_refs] int32 class of every reference, in [0, n_classes)
  *   mode_mask  which search modes to materialise: U8 data allows the exact
  *              modes (F16, BF16, I8), F32 data allows LNBNN_FP8_RERANK
@@ -92,9 +101,10 @@ enum {
  *   out        receives the index; *out is untouched on failure
  *
  * Memory: the packed references stay resident (N x 256 B per FP16/BF16
- * mode, N x 128 B for INT8, N x 128 B FP8 plus N x 512 B FP32 for the
+ * mode, N x dim B for INT8, N x 128 B FP8 plus N x 512 B FP32 for the
  * re-rank), with FP32 norms (4 B) and int32 labels (4 B) per reference.
- * Errors: EINVAL (NULL pointer, dim != 128, n_refs < 1 or >= 2^31-256,
+ * Errors: EINVAL (NULL pointer, dim not 128 or 160, 160 with other data or
+ * modes than u8 INT8, n_refs < 1 or >= 2^31-256,
  * n_classes < 1, label out of range, empty or data-incompatible mode mask),
  * ENOMEM, EDEVICE.  Blocks until the index is resident.
  */

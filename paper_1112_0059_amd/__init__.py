@@ -26,6 +26,7 @@ LNBNN_U8, LNBNN_F32 = 0, 1
 LNBNN_EXACT_F16, LNBNN_EXACT_BF16, LNBNN_FP8_RERANK, LNBNN_EXACT_I8 = 0, 1, 2, 3
 LNBNN_DEVICE_PTRS, LNBNN_PER_IMAGE_LAUNCH, LNBNN_NO_GRAPH, LNBNN_TIMING = 1, 2, 4, 8
 LNBNN_DIM = 128
+LNBNN_DIM_LOC = 160
 LNBNN_MAX_K = 32
 
 
@@ -147,14 +148,21 @@ def _dtype_code(x) -> int:
     raise TypeError(f"descriptors must be uint8 or float32, got {x.dtype}")
 
 
+def _check_width(ix, queries):
+    """Queries are read as [n, dim] rows of the index's width."""
+    if len(queries.shape) != 2 or int(queries.shape[1]) != ix.dim:
+        raise LnbnnError(LNBNN_EINVAL, f"queries must be [n, {ix.dim}], got {tuple(queries.shape)}")
+
+
 class Index:
     """Owner of an lnbnn_index handle."""
 
-    def __init__(self, handle, n_refs: int, n_classes: int, dtype: int):
+    def __init__(self, handle, n_refs: int, n_classes: int, dtype: int, dim: int = LNBNN_DIM):
         self.handle = handle
         self.n_refs = n_refs
         self.n_classes = n_classes
         self.dtype = dtype
+        self.dim = dim
 
     def free(self):
         if self.handle:
@@ -185,7 +193,7 @@ def lnbnn_build_index(refs, labels, n_classes: int, mode_mask: int, hbm_budget_b
                                     int(n_classes), int(mode_mask), int(hbm_budget_bytes),
                                     LNBNN_DEVICE_PTRS if dev else 0, _stream(refs, stream),
                                     ctypes.byref(out)))
-    return Index(out, n_refs, int(n_classes), _dtype_code(refs))
+    return Index(out, n_refs, int(n_classes), _dtype_code(refs), dim)
 
 
 def lnbnn_index_free(ix: Index):
@@ -215,6 +223,7 @@ def lnbnn_classify(ix: Index, queries, img_offsets, k: int, mode: int, flags: in
     n_img = offsets.shape[0] - 1
     n_q = int(offsets[-1]) if n_img >= 0 else 0
     kp = k + 1
+    _check_width(ix, queries)
     float_totals = mode == LNBNN_FP8_RERANK
     dev = _is_torch(queries)
     if dev:
@@ -256,6 +265,7 @@ def lnbnn_last_timing(ix: Index) -> dict:
 def lnbnn_autotune(ix: Index, queries_dev, img_offsets, k: int, mode: int,
                    cache_path: str | None = None, stream=None) -> int:
     offsets = np.ascontiguousarray(img_offsets, dtype=np.int64)
+    _check_width(ix, queries_dev)
     best = ctypes.c_int32(-1)
     _check(load().lnbnn_autotune(ix.handle, _ptr(queries_dev), _dtype_code(queries_dev),
                                  _ptr(offsets), offsets.shape[0] - 1, int(k), int(mode),
@@ -288,6 +298,7 @@ def lnbnn_serve_config(ix: Index, max_batch_desc: int = 0, max_inflight: int = 0
 
 def lnbnn_submit(ix: Index, queries, k: int, mode: int) -> int:
     queries = np.ascontiguousarray(queries)
+    _check_width(ix, queries)
     t = ctypes.c_uint64()
     _check(load().lnbnn_submit(ix.handle, _ptr(queries), _dtype_code(queries),
                                int(queries.shape[0]), int(k), int(mode), ctypes.byref(t)))

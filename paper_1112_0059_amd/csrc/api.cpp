@@ -50,7 +50,7 @@ static hipError_t dmalloc(void **p, size_t bytes)
     return hipMalloc(p, bytes);
 }
 
-int64_t row_bytes(int dtype) { return dtype == LNBNN_U8 ? kDim : kDim * 4; }
+int64_t row_bytes(int dtype, int dim) { return dtype == LNBNN_U8 ? dim : (int64_t)dim * 4; }
 
 int mode_fmt(int mode)
 {
@@ -61,6 +61,12 @@ int mode_fmt(int mode)
     case LNBNN_EXACT_I8: return FMT_I8;
     }
     return -1;
+}
+
+int index_fmt(const lnbnn_index *ix, int mode)
+{
+    const int f = mode_fmt(mode);
+    return f == FMT_I8 && ix->dim == kDimLoc ? FMT_I8L : f;
 }
 
 Workspace::~Workspace()
@@ -188,6 +194,7 @@ static int blocks_per_cu(lnbnn_index *ix, int v, int fmt, int kpb)
 static int default_variant(int fmt, int kp)
 {
     if (fmt == FMT_FP8) return variant_supports(4, fmt, kp) ? 4 : variant_supports(6, fmt, kp) ? 6 : 0;
+    if (fmt == FMT_I8L) return variant_supports(10, fmt, kp) ? 10 : 11;
     // 8 waves x 64 queries share each LDS stage (half the reference traffic
     // of 4-wave workgroups); 32 queries per wave where the longer neighbour
     // lists need the registers.
@@ -197,7 +204,7 @@ static int default_variant(int fmt, int kp)
 
 int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_variant, Plan *out)
 {
-    const int fmt = mode_fmt(mode);
+    const int fmt = index_fmt(ix, mode);
     const int kpb = kp_bucket(kp, fmt);
     if (kpb == 0) return set_err(LNBNN_EINVAL, "k + 1 = %d is not supported by mode %d", kp, mode);
     lnbnn_tuning tu{-1, 0, 0};
@@ -304,7 +311,8 @@ int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t
     } else {
         FinishArgs f{};
         f.q = io.q;
-        f.q_shift = p.fmt == FMT_I8 ? 128 : 0;
+        f.q_shift = p.fmt == FMT_I8 || p.fmt == FMT_I8L ? 128 : 0;
+        f.dim = ix->dim;
         f.bd = io.bd;
         f.offsets = io.offsets;
         f.labels = ix->labels;
@@ -333,7 +341,7 @@ int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t
 // ===========================================================================
 static int free_index_buffers(lnbnn_index *ix)
 {
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < kNumFmt; ++f) {
         if (ix->frag[f]) (void)hipFree(ix->frag[f]);
         ix->frag[f] = nullptr;
     }
@@ -342,7 +350,8 @@ static int free_index_buffers(lnbnn_index *ix)
     else if (ix->seed[FMT_BF16]) (void)hipFree(ix->seed[FMT_BF16]);
     if (ix->seed[FMT_FP8]) (void)hipFree(ix->seed[FMT_FP8]);
     if (ix->seed[FMT_I8]) (void)hipFree(ix->seed[FMT_I8]);
-    for (int f = 0; f < 4; ++f) ix->seed[f] = nullptr;
+    if (ix->seed[FMT_I8L]) (void)hipFree(ix->seed[FMT_I8L]);
+    for (int f = 0; f < kNumFmt; ++f) ix->seed[f] = nullptr;
     if (ix->parity) (void)hipFree(ix->parity);
     ix->parity = nullptr;
     if (ix->labels) (void)hipFree(ix->labels);
@@ -360,7 +369,11 @@ extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, in
                                  lnbnn_index **out)
 {
     if (!out || !refs || !labels) return set_err(LNBNN_EINVAL, "NULL argument");
-    if (dim != LNBNN_DIM) return set_err(LNBNN_EINVAL, "dim must be %d (got %d)", LNBNN_DIM, dim);
+    if (dim != LNBNN_DIM && dim != LNBNN_DIM_LOC)
+        return set_err(LNBNN_EINVAL, "dim must be %d or %d (got %d)", LNBNN_DIM, LNBNN_DIM_LOC, dim);
+    if (dim == LNBNN_DIM_LOC && (dtype != LNBNN_U8 || mode_mask != LNBNN_MODE_BIT(LNBNN_EXACT_I8)))
+        return set_err(LNBNN_EINVAL, "dim %d (location-augmented) needs u8 data and the INT8 mode alone",
+                       LNBNN_DIM_LOC);
     if (n_refs < 1 || n_refs >= (int64_t)0x7fffffff - kPadRows)
         return set_err(LNBNN_EINVAL, "n_refs out of range: %lld", (long long)n_refs);
     if (n_classes < 1) return set_err(LNBNN_EINVAL, "n_classes must be >= 1");
@@ -387,6 +400,7 @@ extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, in
     std::unique_ptr<lnbnn_index> ix(new lnbnn_index());
     ix->device = dev;
     ix->dtype = dtype;
+    ix->dim = dim;
     ix->n_refs = n_refs;
     ix->n_pad = (n_refs + kPadRows - 1) / kPadRows * kPadRows;
     ix->n_classes = n_classes;
@@ -424,7 +438,7 @@ extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, in
     }
 
     // references: stage the rows on the device, then pack per mode
-    const int64_t rbytes = n_refs * row_bytes(dtype);
+    const int64_t rbytes = n_refs * row_bytes(dtype, dim);
     const void *d_refs = refs;
     void *staged = nullptr;
     if (dtype == LNBNN_F32) {
@@ -476,14 +490,15 @@ extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, in
     }
     if (!rc && dtype == LNBNN_U8 && (mode_mask & LNBNN_MODE_BIT(LNBNN_EXACT_I8))) {
         // INT8 mode: its own fragments, seeds and parity masks
+        const int f8 = index_fmt(ix.get(), LNBNN_EXACT_I8);
         int32_t *iseed = nullptr;
-        rc = grow((void **)&ix->frag[FMT_I8], 0, ix->n_pad * kDim, 1);
+        rc = grow((void **)&ix->frag[f8], 0, ix->n_pad * dim, 1);
         if (!rc) rc = grow((void **)&iseed, 0, ix->n_pad, 4);
-        if (!rc) ix->seed[FMT_I8] = reinterpret_cast<float *>(iseed);
+        if (!rc) ix->seed[f8] = reinterpret_cast<float *>(iseed);
         if (!rc) rc = grow((void **)&ix->parity, 0, ix->n_pad / kTileRows, 4);
         if (!rc) {
-            bytes += ix->n_pad * (kDim + 4) + ix->n_pad / kTileRows * 4;
-            hipError_t e = launch_pack_i8(static_cast<const uint8_t *>(d_refs), n_refs, ix->n_pad, ix->frag[FMT_I8],
+            bytes += ix->n_pad * (dim + 4) + ix->n_pad / kTileRows * 4;
+            hipError_t e = launch_pack_i8(static_cast<const uint8_t *>(d_refs), n_refs, ix->n_pad, dim, ix->frag[f8],
                                           iseed, ix->parity, s);
             if (e != hipSuccess) rc = hip_err(e, "pack i8");
         }
@@ -625,7 +640,7 @@ static int classify_per_image(lnbnn_index *ix, const void *dq, const int64_t *of
     }
     LN_HIP(hipMemcpyAsync(ws.bd, bds.data(), n_images * sizeof(BatchDesc), hipMemcpyHostToDevice, s));
     LN_HIP(hipMemcpyAsync(ws.offsets, offs.data(), offs.size() * 8, hipMemcpyHostToDevice, s));
-    const int64_t rb = row_bytes(ix->dtype);
+    const int64_t rb = row_bytes(ix->dtype, ix->dim);
     double kms = 0;
     for (int32_t m = 0; m < n_images; ++m) {
         BatchIO io;
@@ -683,7 +698,7 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
     const bool fp8 = mode == LNBNN_FP8_RERANK;
     const int list_len = dist_list_len(mode, k);   // what the distance kernel keeps
     const int64_t n_q = img_offsets[n_images];
-    const int64_t rb = row_bytes(dtype);
+    const int64_t rb = row_bytes(dtype, ix->dim);
     const int64_t nc = ix->n_classes;
 
     Plan plan;
@@ -814,7 +829,7 @@ extern "C" int lnbnn_set_tuning(lnbnn_index *ix, int mode, int32_t k, const lnbn
     if (k < 1 || k > LNBNN_MAX_K) return set_err(LNBNN_EINVAL, "bad k");
     if (t->chunk_tiles < 0 || t->chunk_tiles % 8 != 0) return set_err(LNBNN_EINVAL, "chunk_tiles must be a multiple of 8");
     if (t->max_workgroups < 0) return set_err(LNBNN_EINVAL, "negative max_workgroups");
-    const int fmt = mode_fmt(mode);
+    const int fmt = index_fmt(ix, mode);
     const int list_len = dist_list_len(mode, k);
     const int kpb = kp_bucket(list_len, fmt);
     if (kpb == 0) return set_err(LNBNN_EINVAL, "k = %d is not supported by mode %d", k, mode);
@@ -876,7 +891,7 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
     int rc = validate_classify(ix, queries_dev, dtype, img_offsets, n_images, k, mode, LNBNN_DEVICE_PTRS, true,
                                nullptr, nullptr);
     if (rc) return rc;
-    const int fmt = mode_fmt(mode);
+    const int fmt = index_fmt(ix, mode);
     const int kpb = kp_bucket(dist_list_len(mode, k), fmt);
     char arch[64] = "gfx";
     {
@@ -884,7 +899,7 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
         if (hipGetDeviceProperties(&prop, ix->device) == hipSuccess) snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
     }
     std::ostringstream key;
-    key << "arch=" << arch << ",n_refs=" << ix->n_refs << ",dim=" << kDim << ",kp=" << kpb << ",mode=" << mode;
+    key << "arch=" << arch << ",n_refs=" << ix->n_refs << ",dim=" << ix->dim << ",kp=" << kpb << ",mode=" << mode;
     if (cache_path) {
         auto m = read_cache(cache_path);
         auto it = m.find(key.str());

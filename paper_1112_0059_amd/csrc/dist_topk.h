@@ -71,6 +71,7 @@ static __device__ __forceinline__ int min16(const i32x16 &a)
 // Float formats: the accumulator is the ranking key d' itself.  The gate
 // compares a tile's smallest key with the list's KP-th key.
 struct FloatKeys {
+    static constexpr int kRow = kDim;     // elements per descriptor
     using acc_t = f32x16;
     using gate_t = float;
     static constexpr bool kParity = false;
@@ -200,10 +201,14 @@ struct OpFP8 : FloatKeys {
 // mask that only the (rare) insertion path reads.  A K step covers 32
 // elements: lane l supplies 16 bytes of row (l & 31), K elements
 // 32*s + 16*(l >> 5) + e.  Padding rows carry the seed 2^30, whose D never
-// makes a key (see key()).
-struct OpI8 {
-    static constexpr int kFmt = FMT_I8;
-    static constexpr int kSteps = 4;
+// makes a key (see key()).  S K steps: S = 4 for 128-element rows, S = 5
+// for the 160-element location-augmented rows (|D| < 2^23 there, and every
+// key and distance stays below 2^24, still exact in FP32).
+template <int S, int FMT>
+struct OpI8T {
+    static constexpr int kFmt = FMT;
+    static constexpr int kSteps = S;
+    static constexpr int kRow = 32 * S;      // bytes per descriptor
     static constexpr int kAU = 1;
     static constexpr bool kScaled = false;
     using acc_t = i32x16;
@@ -231,7 +236,7 @@ struct OpI8 {
     static __device__ __forceinline__ void load_b(const void *q, const int32_t *, int64_t qi, bool ok, int h,
                                                   uint4 (&b)[kSteps][kAU], int &sb)
     {
-        const uint4 *qrow = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(q) + (ok ? qi : 0) * kDim);
+        const uint4 *qrow = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(q) + (ok ? qi : 0) * kRow);
 #pragma unroll
         for (int s = 0; s < kSteps; ++s) {
             // bytes 127 - q: q ^ 0x7f reads as that int8 for every q in 0..255
@@ -256,6 +261,8 @@ struct OpI8 {
                                                      c, 0, 0, 0);
     }
 };
+using OpI8 = OpI8T<4, FMT_I8>;
+using OpI8L = OpI8T<5, FMT_I8L>;
 
 // ---------------------------------------------------------------------------
 // K1: distances + top-(k+1).
@@ -660,7 +667,7 @@ void k_dist_topk(DistArgs a)
     constexpr int QB = W * QW;                    // queries per workgroup
     constexpr int PD = NB - 1;                    // stages in flight ahead of the one computed
     constexpr int LPS = StageLoads<Op, MT, W>::total;   // loads per wave per stage
-    constexpr bool kPrefetch = Op::kSteps * Op::kAU == 4;      // 4 KB tiles leave registers for it
+    constexpr bool kPrefetch = Op::kSteps * Op::kAU <= 5;      // 4-5 KB tiles leave registers for it
     // With 3+ buffers the 4 KB-tile path synchronises per buffer instead of
     // per stage: PF = NB - 2 stages in flight leave one stage of slack, so a
     // wave that inserts delays only itself.
@@ -936,38 +943,51 @@ static void *kernel_ptr()
 template <class Op, int KP>
 static void *pick_variant(int v)
 {
-    switch (v) {
-    case 0: return kernel_ptr<Op, KP, 1, 2, 4, 4>();
-    }
-    if constexpr (KP <= 40)
-        if (v == 6) return kernel_ptr<Op, KP, 1, 4, 8, 4>();
-    if constexpr (Op::kFmt == FMT_FP8) {
-        if constexpr (KP <= 20) {
+    if constexpr (Op::kFmt == FMT_I8L) {
+        // 5 KB tiles: a stage of MT tiles splits into 1 KB copies evenly
+        // over the waves only for MT * 5 a multiple of W, and four 8-tile
+        // buffers would not fit in LDS
+        if constexpr (KP <= 16) {
+            switch (v) {
+            case 2: return kernel_ptr<Op, KP, 2, 4, 4, 2>();
+            case 7: return kernel_ptr<Op, KP, 2, 4, 4, 3>();
+            case 10: return kernel_ptr<Op, KP, 2, 8, 8, 3>();
+            }
+        }
+        if (v == 11) return kernel_ptr<Op, KP, 1, 8, 8, 3>();
+        return nullptr;
+    } else {
+        if (v == 0) return kernel_ptr<Op, KP, 1, 2, 4, 4>();
+        if constexpr (KP <= 40)
+            if (v == 6) return kernel_ptr<Op, KP, 1, 4, 8, 4>();
+        if constexpr (Op::kFmt == FMT_FP8) {
+            if constexpr (KP <= 20) {
+                switch (v) {
+                case 1: return kernel_ptr<Op, KP, 2, 2, 4, 4>();
+                case 4: return kernel_ptr<Op, KP, 2, 4, 8, 4>();
+                case 5: return kernel_ptr<Op, KP, 2, 2, 8, 8>();
+                case 8: return kernel_ptr<Op, KP, 2, 8, 8, 4>();
+                case 9: return kernel_ptr<Op, KP, 2, 4, 8, 8>();
+                }
+            }
+        } else if constexpr (KP <= 16) {
             switch (v) {
             case 1: return kernel_ptr<Op, KP, 2, 2, 4, 4>();
+            case 2: return kernel_ptr<Op, KP, 2, 4, 4, 2>();
+            case 3: return kernel_ptr<Op, KP, 2, 2, 4, 2>();
             case 4: return kernel_ptr<Op, KP, 2, 4, 8, 4>();
             case 5: return kernel_ptr<Op, KP, 2, 2, 8, 8>();
-            case 8: return kernel_ptr<Op, KP, 2, 8, 8, 4>();
-            case 9: return kernel_ptr<Op, KP, 2, 4, 8, 8>();
+            case 7: return kernel_ptr<Op, KP, 2, 4, 4, 3>();
+            }
+            if constexpr (Op::kSteps * Op::kAU == 4) {      // 4 KB tiles
+                switch (v) {
+                case 8: return kernel_ptr<Op, KP, 2, 8, 8, 4>();
+                case 9: return kernel_ptr<Op, KP, 2, 4, 8, 8>();
+                }
             }
         }
-    } else if constexpr (KP <= 16) {
-        switch (v) {
-        case 1: return kernel_ptr<Op, KP, 2, 2, 4, 4>();
-        case 2: return kernel_ptr<Op, KP, 2, 4, 4, 2>();
-        case 3: return kernel_ptr<Op, KP, 2, 2, 4, 2>();
-        case 4: return kernel_ptr<Op, KP, 2, 4, 8, 4>();
-        case 5: return kernel_ptr<Op, KP, 2, 2, 8, 8>();
-        case 7: return kernel_ptr<Op, KP, 2, 4, 4, 3>();
-        }
-        if constexpr (Op::kSteps * Op::kAU == 4) {      // 4 KB tiles
-            switch (v) {
-            case 8: return kernel_ptr<Op, KP, 2, 8, 8, 4>();
-            case 9: return kernel_ptr<Op, KP, 2, 4, 8, 8>();
-            }
-        }
+        return nullptr;
     }
-    return nullptr;
 }
 
 }  // namespace lnbnn

@@ -8,13 +8,16 @@
 namespace lnbnn {
 
 constexpr int kDim = 128;
+constexpr int kDimLoc = 160;             // location-augmented descriptors (INT8 mode only)
 constexpr int kTileRows = 32;            // rows of one MFMA A tile
 constexpr int kPadRows = 256;            // index rows are padded to this multiple
 constexpr int kMaxKP = 33;               // k + 1 <= 33
 constexpr int kMaxFp8K = 32;             // FP8 mode re-ranks 4k <= 128 candidates
 
-// Element formats of the packed reference tiles.
-enum Fmt { FMT_F16 = 0, FMT_BF16 = 1, FMT_FP8 = 2, FMT_I8 = 3 };
+// Element formats of the packed reference tiles (FMT_I8L: INT8 tiles of
+// 160-element rows, five K steps).
+enum Fmt { FMT_F16 = 0, FMT_BF16 = 1, FMT_FP8 = 2, FMT_I8 = 3, FMT_I8L = 4 };
+constexpr int kNumFmt = 5;
 
 // Batch shape read on the device, so one captured launch sequence serves
 // every batch up to the capacity it was captured for.
@@ -75,7 +78,8 @@ struct RerankArgs {
 };
 
 struct FinishArgs {
-    const void *q;              // u8 queries (for ||q - shift||^2)
+    const void *q;              // u8 queries [n_q, dim] (for ||q - shift||^2)
+    int32_t dim;                // 128, or 160 (location-augmented, INT8 mode)
     int32_t q_shift;            // 0, or 128 where the keys are those of r - 128 and q - 128
     const BatchDesc *bd;
     const int64_t *offsets;     // device [n_img + 1]
@@ -121,6 +125,12 @@ int kp_bucket(int kp, int fmt);         // list length compiled for kp (0 = unsu
     X(i8, OpI8, FMT_I8, 16)       \
     X(i8, OpI8, FMT_I8, 21)       \
     X(i8, OpI8, FMT_I8, 33)       \
+    X(i8l, OpI8L, FMT_I8L, 2)     \
+    X(i8l, OpI8L, FMT_I8L, 6)     \
+    X(i8l, OpI8L, FMT_I8L, 11)    \
+    X(i8l, OpI8L, FMT_I8L, 16)    \
+    X(i8l, OpI8L, FMT_I8L, 21)    \
+    X(i8l, OpI8L, FMT_I8L, 33)    \
     X(fp8, OpFP8, FMT_FP8, 4)     \
     X(fp8, OpFP8, FMT_FP8, 8)     \
     X(fp8, OpFP8, FMT_FP8, 20)    \
@@ -130,8 +140,8 @@ int kp_bucket(int kp, int fmt);         // list length compiled for kp (0 = unsu
 // Upload-side packing.  refs_u8 / refs_f32 are device pointers.
 hipError_t launch_pack_u8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, int fmt,
                           uint4 *frag, float *seed, hipStream_t s);
-hipError_t launch_pack_i8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, uint4 *frag, int32_t *seed,
-                          uint32_t *parity, hipStream_t s);
+hipError_t launch_pack_i8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, int dim, uint4 *frag,
+                          int32_t *seed, uint32_t *parity, hipStream_t s);
 hipError_t launch_fp8_index(const float *refs, int64_t n_refs, int64_t n_pad, uint4 *frag, float *seed,
                             int32_t *row_scale, hipStream_t s);
 hipError_t launch_fp8_qprep(const float *q, const BatchDesc *bd, int64_t q_cap, uint4 *q8, int32_t *qsc,

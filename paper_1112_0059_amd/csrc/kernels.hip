@@ -13,9 +13,10 @@
 namespace lnbnn {
 
 // ---------------------------------------------------------------------------
-// K0: packing of u8 references.  Fragment u = (tile * kSteps + s) * 64 + lane
-// holds the K elements lane `lane` supplies at step s for row
-// 32*tile + (lane & 31) (eight FP16/BF16 values, or sixteen int8 values).
+// K0: packing of u8 references ([n_refs, Op::kRow] bytes).  Fragment
+// u = (tile * kSteps + s) * 64 + lane holds the K elements lane `lane`
+// supplies at step s for row 32*tile + (lane & 31) (eight FP16/BF16 values,
+// or sixteen int8 values).
 // ---------------------------------------------------------------------------
 template <class Op>
 __global__ void k_pack_u8(const uint8_t *__restrict__ refs, int64_t n_refs, int64_t n_frag,
@@ -28,22 +29,22 @@ __global__ void k_pack_u8(const uint8_t *__restrict__ refs, int64_t n_refs, int6
         const int64_t tile = (u >> 6) / Op::kSteps;
         const int64_t row = tile * kTileRows + (lane & 31);
         const bool ok = row < n_refs;
-        frag[u] = Op::pack_frag(refs + (ok ? row : 0) * kDim, ok, s, lane >> 5);
+        frag[u] = Op::pack_frag(refs + (ok ? row : 0) * Op::kRow, ok, s, lane >> 5);
     }
 }
 
-// INT8 seeds: floor(||s||^2 / 2) + sum(s) with s = r - 128 (stored as the
-// int32 bit pattern), 2^30 on padding rows; and per 32-row tile the mask of
-// the rows' ||s||^2 parities (= parity of sum(r)).
-__global__ void k_seed_i8(const uint8_t *__restrict__ refs, int64_t n_refs, int64_t n_pad,
+// INT8 seeds of [n_refs, dim] references: floor(||s||^2 / 2) + sum(s) with
+// s = r - 128 (stored as the int32 bit pattern), 2^30 on padding rows; and
+// per 32-row tile the mask of the rows' ||s||^2 parities (= parity of sum(r)).
+__global__ void k_seed_i8(const uint8_t *__restrict__ refs, int64_t n_refs, int64_t n_pad, int dim,
                           int32_t *__restrict__ seed, uint32_t *__restrict__ parity)
 {
     for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < n_pad;
          row += (int64_t)gridDim.x * blockDim.x) {
         int32_t sq = 0, sum = 0;
         if (row < n_refs) {
-            const uint4 *p = reinterpret_cast<const uint4 *>(refs + row * kDim);
-            for (int c = 0; c < kDim / 16; ++c) {
+            const uint4 *p = reinterpret_cast<const uint4 *>(refs + row * dim);
+            for (int c = 0; c < dim / 16; ++c) {
                 const uint4 v = p[c];
                 const uint32_t w[4] = {v.x, v.y, v.z, v.w};
                 for (int i = 0; i < 4; ++i)
@@ -134,9 +135,9 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs a)
             ii[p] = bi;
         }
         // ||q - shift||^2 turns the key back into the squared distance
-        const uint4 *qr = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(a.q) + q * kDim);
+        const uint4 *qr = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(a.q) + q * a.dim);
         uint32_t qq = 0;
-        for (int c = 0; c < kDim / 16; ++c) {
+        for (int c = 0; c < a.dim / 16; ++c) {
             const uint4 v = qr[c];
             const uint32_t w[4] = {v.x, v.y, v.z, v.w};
             for (int i = 0; i < 4; ++i)
@@ -230,10 +231,12 @@ static const Variant kVariants[] = {
     {2, 4, 4, 3},   // 7
     {2, 8, 8, 4},   // 8  (4 KB tiles only: INT8, FP8)
     {2, 4, 8, 8},   // 9  (4 KB tiles only: INT8, FP8)
+    {2, 8, 8, 3},   // 10 (160-element INT8 rows only)
+    {1, 8, 8, 3},   // 11 (160-element INT8 rows only)
 };
 static const char *kVariantNames[] = {"w4_nt1_mt2_nb4", "w4_nt2_mt2_nb4", "w4_nt2_mt4_nb2", "w4_nt2_mt2_nb2",
                                       "w8_nt2_mt4_nb4", "w8_nt2_mt2_nb8", "w8_nt1_mt4_nb4", "w4_nt2_mt4_nb3",
-                                      "w8_nt2_mt8_nb4", "w8_nt2_mt4_nb8"};
+                                      "w8_nt2_mt8_nb4", "w8_nt2_mt4_nb8", "w8_nt2_mt8_nb3", "w8_nt1_mt8_nb3"};
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int num_variants() { return kNumVariants; }
@@ -242,7 +245,7 @@ const char *variant_name(int v) { return (v >= 0 && v < kNumVariants) ? kVariant
 
 int kp_bucket(int kp, int fmt)
 {
-    if (fmt == FMT_F16 || fmt == FMT_BF16 || fmt == FMT_I8) {
+    if (fmt == FMT_F16 || fmt == FMT_BF16 || fmt == FMT_I8 || fmt == FMT_I8L) {
         static const int b[] = {2, 6, 11, 16, 21, 33};
         for (int x : b)
             if (kp <= x) return x;
@@ -259,6 +262,10 @@ bool variant_supports(int v, int fmt, int kp)
     if (v < 0 || v >= kNumVariants) return false;
     const int b = kp_bucket(kp, fmt);
     if (b == 0) return false;
+    // 5 KB tiles (160-element INT8 rows) split evenly over the waves only
+    // in these stage shapes
+    if (fmt == FMT_I8L) return v == 11 || ((v == 2 || v == 7 || v == 10) && b <= 16);
+    if (v == 10 || v == 11) return false;
     // the deep stage variants need the 4 KB tiles of the 8-bit formats
     if ((v == 8 || v == 9) && (fmt == FMT_F16 || fmt == FMT_BF16)) return false;
     // 64-entry lists take a SIMD's whole register file: one wave per SIMD
@@ -335,15 +342,23 @@ hipError_t launch_pack_u8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, in
     return e;
 }
 
-hipError_t launch_pack_i8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, uint4 *frag, int32_t *seed,
-                          uint32_t *parity, hipStream_t s)
+hipError_t launch_pack_i8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, int dim, uint4 *frag,
+                          int32_t *seed, uint32_t *parity, hipStream_t s)
 {
-    const int64_t n_frag = (n_pad / kTileRows) * OpI8::kSteps * 64;
-    k_pack_u8<OpI8><<<grid_for(n_frag, 256, 65536), 256, 0, s>>>(refs, n_refs, n_frag, frag);
+    if (dim == kDim) {
+        const int64_t n_frag = (n_pad / kTileRows) * OpI8::kSteps * 64;
+        k_pack_u8<OpI8><<<grid_for(n_frag, 256, 65536), 256, 0, s>>>(refs, n_refs, n_frag, frag);
+    } else if (dim == kDimLoc) {
+        const int64_t n_frag = (n_pad / kTileRows) * OpI8L::kSteps * 64;
+        k_pack_u8<OpI8L><<<grid_for(n_frag, 256, 65536), 256, 0, s>>>(refs, n_refs, n_frag, frag);
+    } else {
+        return hipErrorInvalidValue;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // whole waves over whole tiles: n_pad is a multiple of 64
-    k_seed_i8<<<grid_for(n_pad, 256, 65536), 256, 0, s>>>(refs, n_refs, n_pad, seed, parity);
+    // whole waves over whole tiles: n_pad is a multiple of 256, as is the
+    // grid stride
+    k_seed_i8<<<grid_for(n_pad, 256, 65536), 256, 0, s>>>(refs, n_refs, n_pad, dim, seed, parity);
     return hipGetLastError();
 }
 

@@ -107,6 +107,7 @@ struct Server;
 struct lnbnn_index {
     int device = 0;
     int dtype = 0;
+    int dim = lnbnn::kDim;          // 128, or 160 (location-augmented, INT8 mode only)
     int64_t n_refs = 0;
     int64_t n_pad = 0;
     int32_t n_classes = 0;
@@ -115,8 +116,8 @@ struct lnbnn_index {
     int cu_count = 0;
     hipStream_t own_stream = nullptr;
 
-    uint4 *frag[4] = {nullptr, nullptr, nullptr, nullptr};
-    float *seed[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint4 *frag[lnbnn::kNumFmt] = {};
+    float *seed[lnbnn::kNumFmt] = {};
     int32_t *labels = nullptr;
     float *ref_f32 = nullptr;       // FP8 mode: FP32 references for the re-rank
     int32_t *row_scale = nullptr;   // FP8 mode: E8M0 exponent of every padded row
@@ -142,6 +143,7 @@ struct lnbnn_index {
 namespace lnbnn {
 
 int mode_fmt(int mode);
+int index_fmt(const lnbnn_index *ix, int mode);   // mode_fmt, with the 160-element INT8 tiles where they apply
 int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_variant, Plan *out);
 int64_t part_elems(const Plan &p, int64_t q_cap);
 // Enqueue fill + distance kernel + finish + argmin for one batch.  When
@@ -153,7 +155,7 @@ int ensure_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int64_t img_cap, in
 int ensure_fp8_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int n_cand, int k);
 int fp8_candidates(int k);
 int dist_list_len(int mode, int k);
-int64_t row_bytes(int dtype);
+int64_t row_bytes(int dtype, int dim);
 
 int launch_graph(std::map<std::string, GraphEntry> &graphs, lnbnn_index *ix, const Plan &p, const BatchIO &io,
                  hipStream_t s);

@@ -86,7 +86,10 @@ struct Server {
     int64_t pending = 0;                  // tickets not yet consumed
 };
 
-static int64_t row_bytes_for_mode(int mode) { return mode == LNBNN_FP8_RERANK ? kDim * 4 : kDim; }
+static int64_t row_bytes_for_mode(const lnbnn_index *ix, int mode)
+{
+    return row_bytes(mode == LNBNN_FP8_RERANK ? LNBNN_F32 : LNBNN_U8, ix->dim);
+}
 
 // Device bytes of one slot for `cap` descriptors and `img_cap` images.
 static int64_t slot_bytes(lnbnn_index *ix, int64_t cap, int64_t img_cap)
@@ -96,7 +99,7 @@ static int64_t slot_bytes(lnbnn_index *ix, int64_t cap, int64_t img_cap)
     const int kmax = fp8 ? kMaxFp8K : LNBNN_MAX_K;
     const int list = kp_bucket(dist_list_len(fp8 ? LNBNN_FP8_RERANK : 0, kmax), fp8 ? FMT_FP8 : FMT_F16);
     const int64_t slices = 32;   // upper bound of the plan's split
-    int64_t b = cap * row_bytes_for_mode(fp8 ? LNBNN_FP8_RERANK : 0);
+    int64_t b = cap * row_bytes_for_mode(ix, fp8 ? LNBNN_FP8_RERANK : 0);
     b += slices * 2 * cap * (int64_t)list * 8;
     b += img_cap * (16 + 8 + ix->n_classes * 16 + 4) + 16;
     if (fp8) b += cap * (kDim + 4) + cap * (int64_t)fp8_candidates(kmax) * 4 + cap * kmax * 12;
@@ -126,7 +129,7 @@ static int setup_slot(Server *sv, Slot *sl)
             }
         }
     }
-    const int64_t rb = row_bytes_for_mode(fp8 ? LNBNN_FP8_RERANK : 0);
+    const int64_t rb = row_bytes_for_mode(ix, fp8 ? LNBNN_FP8_RERANK : 0);
     int rc = ensure_ws(ix, sl->ws, cap, img, part, 0, cap * rb, fp8);
     if (rc) return rc;
     if (fp8 && (rc = ensure_fp8_ws(ix, sl->ws, cap, fp8_candidates(kmax), kmax))) return rc;
@@ -157,7 +160,7 @@ static int launch_slot(Server *sv, Slot *sl)
     const int mode = sl->batch[0]->mode;
     const int k = sl->batch[0]->k;
     const bool fp8 = mode == LNBNN_FP8_RERANK;
-    const int64_t rb = row_bytes_for_mode(mode);
+    const int64_t rb = row_bytes_for_mode(ix, mode);
     int64_t n_q = 0;
     sl->h_off[0] = 0;
     for (size_t i = 0; i < sl->batch.size(); ++i) {
@@ -417,7 +420,7 @@ extern "C" int lnbnn_submit(lnbnn_index *ix, const void *queries, int dtype, int
     r->mode = mode;
     r->st.t_submit_ns = now_ns();
     r->st.n_desc = (int32_t)n_desc;
-    const int64_t bytes = n_desc * row_bytes_for_mode(mode);
+    const int64_t bytes = n_desc * row_bytes_for_mode(ix, mode);
     r->data.assign(static_cast<const uint8_t *>(queries), static_cast<const uint8_t *>(queries) + bytes);
     {
         std::lock_guard<std::mutex> l2(sv->mu);

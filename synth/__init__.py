@@ -30,6 +30,19 @@ Recipe (every config):
   * generation is chunked (65536 descriptors per chunk, each chunk its own
     PCG64 stream from SeedSequence(seed, spawn_key=(1, chunk))) so results do
     not depend on the thread count.
+
+Location-augmented u8 sets (the paper weights a descriptor's image location
+by alpha = 1.6, Sec. 6; the augmented form is Boiman et al.'s):
+  * every class prototype has a location centre in [0.15, 0.85]^2 (index
+    seed, spawn key 2); a prototype descriptor lies at its centre plus
+    N(0, 0.08^2) per coordinate, clipped to [0, 1]; a background descriptor
+    anywhere in the unit square (own stream per chunk, spawn key (3, chunk),
+    so the 128 descriptor bytes equal the plain generator's);
+  * a row is 160 bytes: the descriptor, then 16 copies of the x code, then
+    16 of the y code, code = rint(204.8 * coordinate) in 0..205.  u8 SIFT is
+    512 times the unit-norm descriptor, so alpha at that scale is 819.2, and
+    16 copies of 819.2 / 4 make 16 * dcode^2 = (819.2 * dcoord)^2 up to
+    rounding while every byte stays an exact u8.
 """
 from __future__ import annotations
 
@@ -41,6 +54,11 @@ import numpy as np
 
 DIM = 128
 CHUNK = 65536
+ALPHA = 1.6                  # location weight (Sec. 6)
+LOC_COPIES = 16              # copies of each coordinate code
+LOC_SCALE = 512.0            # u8 SIFT units per unit-norm descriptor unit
+DIM_LOC = DIM + 2 * LOC_COPIES
+LOC_SPREAD = 0.08
 
 
 @dataclass(frozen=True)
@@ -121,13 +139,49 @@ def world(cfg: Config):
     return protos.reshape(cfg.n_classes, cfg.n_proto, DIM), bg
 
 
-def _descriptors(cfg: Config, protos, bg, cls: np.ndarray, seed: int, chunk: int, out):
-    """Fill out[chunk rows] for descriptors whose class is cls (one chunk)."""
+def loc_centres(cfg: Config) -> np.ndarray:
+    """Location centre of every class prototype: [n_classes, n_proto, 2]."""
+    rng = _rng(cfg.index_seed, 2)
+    return rng.uniform(0.15, 0.85, size=(cfg.n_classes, cfg.n_proto, 2))
+
+
+def loc_code(xy: np.ndarray) -> np.ndarray:
+    """Coordinates in [0, 1] -> u8 codes rint(alpha * 512 / 4 * x)."""
+    return np.rint(np.asarray(xy, np.float64) * (ALPHA * LOC_SCALE / np.sqrt(LOC_COPIES))).astype(np.uint8)
+
+
+def augment(desc: np.ndarray, xy: np.ndarray) -> np.ndarray:
+    """[n, 128] u8 descriptors and [n, 2] coordinates -> [n, 160] u8 rows."""
+    n = desc.shape[0]
+    out = np.empty((n, DIM_LOC), np.uint8)
+    out[:, :DIM] = desc
+    c = loc_code(xy)
+    out[:, DIM:DIM + LOC_COPIES] = c[:, 0:1]
+    out[:, DIM + LOC_COPIES:] = c[:, 1:2]
+    return out
+
+
+def _locations(cfg: Config, centres, is_bg, cls, pick_pr, seed: int, chunk: int) -> np.ndarray:
+    rng = _rng(seed, 3, chunk)
+    m = cls.shape[0]
+    near = centres[cls, pick_pr] + LOC_SPREAD * rng.standard_normal((m, 2))
+    anywhere = rng.random((m, 2))
+    return np.clip(np.where(is_bg[:, None], anywhere, near), 0.0, 1.0)
+
+
+def _descriptors(cfg: Config, protos, bg, cls: np.ndarray, seed: int, chunk: int, out, centres=None):
+    """Fill out[chunk rows] for descriptors whose class is cls (one chunk);
+    with location centres given, out has DIM_LOC columns."""
     rng = _rng(seed, 1, chunk)
     m = cls.shape[0]
     is_bg = rng.random(m) < cfg.f_bg
     pick_bg = rng.integers(0, cfg.n_bg, size=m)
     pick_pr = rng.integers(0, cfg.n_proto, size=m)
+    if centres is not None:
+        desc = np.empty((m, DIM), np.uint8)
+        _descriptors(cfg, protos, bg, cls, seed, chunk, desc)
+        out[:] = augment(desc, _locations(cfg, centres, is_bg, cls, pick_pr, seed, chunk))
+        return
     means = np.where(is_bg[:, None], bg[pick_bg], protos[cls, pick_pr])
     z = rng.standard_normal(size=(m, DIM), dtype=np.float32)
     x = means.astype(np.float32, copy=False)
@@ -140,16 +194,18 @@ def _descriptors(cfg: Config, protos, bg, cls: np.ndarray, seed: int, chunk: int
         out[:] = _unit_relu(x, rng, lambda k: rng.standard_normal((k, DIM), dtype=np.float32))
 
 
-def _fill(cfg: Config, cls: np.ndarray, seed: int) -> np.ndarray:
+def _fill(cfg: Config, cls: np.ndarray, seed: int, loc: bool = False) -> np.ndarray:
     protos, bg = world(cfg)
+    centres = loc_centres(cfg) if loc else None
+    assert not loc or cfg.kind == "u8"
     n = cls.shape[0]
-    out = np.empty((n, DIM), np.uint8 if cfg.kind == "u8" else np.float32)
+    out = np.empty((n, DIM_LOC if loc else DIM), np.uint8 if cfg.kind == "u8" else np.float32)
     nch = (n + CHUNK - 1) // CHUNK
 
     def job(c):
         s = c * CHUNK
         e = min(n, s + CHUNK)
-        _descriptors(cfg, protos, bg, cls[s:e], seed, c, out[s:e])
+        _descriptors(cfg, protos, bg, cls[s:e], seed, c, out[s:e], centres)
 
     with ThreadPoolExecutor(_threads()) as ex:
         list(ex.map(job, range(nch)))
@@ -162,10 +218,11 @@ def index_labels(cfg: Config) -> np.ndarray:
     return np.repeat(np.arange(cfg.n_classes, dtype=np.int32), per_class)
 
 
-def gen_index(cfg: Config):
-    """(refs [n_refs, DIM] uint8 or float32, labels int32 [n_refs])."""
+def gen_index(cfg: Config, loc: bool = False):
+    """(refs [n_refs, DIM] uint8 or float32, labels int32 [n_refs]); with
+    loc, u8 rows of DIM_LOC bytes (location-augmented)."""
     labels = index_labels(cfg)
-    return _fill(cfg, labels, cfg.index_seed), labels
+    return _fill(cfg, labels, cfg.index_seed, loc), labels
 
 
 def query_layout(cfg: Config):
@@ -181,11 +238,12 @@ def query_layout(cfg: Config):
     return offsets, true_cls
 
 
-def gen_queries(cfg: Config):
-    """(queries [n, DIM], CSR offsets int64 [n_img + 1], true class [n_img])."""
+def gen_queries(cfg: Config, loc: bool = False):
+    """(queries [n, DIM] (DIM_LOC with loc), CSR offsets int64 [n_img + 1],
+    true class [n_img])."""
     offsets, true_cls = query_layout(cfg)
     per_desc = np.repeat(true_cls, np.diff(offsets))
-    return _fill(cfg, per_desc, cfg.query_seed), offsets, true_cls
+    return _fill(cfg, per_desc, cfg.query_seed, loc), offsets, true_cls
 
 
 def gen_query_images(cfg: Config, images):

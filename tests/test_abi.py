@@ -38,6 +38,7 @@ def test_binding_constants_match_header():
         assert m, name
         assert int(m.group(1)) == getattr(L, name), name
     assert f"#define LNBNN_DIM {L.LNBNN_DIM}" in src
+    assert f"#define LNBNN_DIM_LOC {L.LNBNN_DIM_LOC}" in src
     assert f"#define LNBNN_MAX_K {L.LNBNN_MAX_K}" in src
 
 

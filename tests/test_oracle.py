@@ -275,3 +275,24 @@ def test_rejects_bad_arguments():
     with pytest.raises(ValueError):
         oracle.local_nbnn(np.zeros((Q.shape[0], 3), np.int32), np.zeros((Q.shape[0], 3), np.int64),
                           2, labels, 4, np.array([1, Q.shape[0]], np.int64))
+
+
+def test_knn_160_against_full_enumeration():
+    """Location-augmented width (160 elements, full u8 range): every oracle
+    route equals numpy's sorted enumeration of all (distance, index) pairs."""
+    rng = np.random.default_rng(21)
+    R = rng.integers(0, 256, size=(50, 160)).astype(np.uint8)
+    Q = rng.integers(0, 256, size=(9, 160)).astype(np.uint8)
+    R[7] = R[3]                        # a duplicate reference: tie by index
+    Q[2] = R[11]                       # an exact match
+    diff = Q[:, None, :].astype(np.int64) - R[None, :, :].astype(np.int64)
+    full = np.sum(diff * diff, axis=2)
+    for route in ("scan", "sort", "expanded"):
+        if route == "expanded":
+            idx, dist = oracle.knn_expanded(Q, R, 12, chunk=13)
+        else:
+            idx, dist = oracle.knn(Q, R, 12, route=route)
+        for i in range(Q.shape[0]):
+            order = np.lexsort((np.arange(R.shape[0]), full[i]))[:12]
+            assert idx[i].tolist() == order.tolist(), route
+            assert dist[i].tolist() == full[i][order].tolist(), route

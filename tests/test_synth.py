@@ -60,3 +60,37 @@ def test_request_stream():
     assert np.all(np.diff(t) >= 0) and t[0] == 0
     assert n.min() >= 100 and n.max() <= 8000
     assert 1200 < np.median(n) < 1800
+
+
+def test_location_augmented_rows():
+    """Layout of the 160-byte rows and what their distance carries: the
+    descriptor part equals the plain generator's, the location part holds 16
+    copies of each coordinate code (at most 205), and the squared distance
+    splits into the descriptor distance plus 16 times the squared code
+    differences, which approximates (alpha * 512 * dcoord)^2."""
+    cfg = synth.scaled(synth.CONFIGS["T"], n_classes=4, n_train=2, n_desc=100, n_img=3, q_lo=50, q_hi=50)
+    R, labels = synth.gen_index(cfg)
+    RL, labels2 = synth.gen_index(cfg, loc=True)
+    assert RL.shape == (R.shape[0], synth.DIM_LOC) and RL.dtype == np.uint8
+    assert np.array_equal(RL[:, :128], R) and np.array_equal(labels, labels2)
+    assert np.all(RL[:, 128:144] == RL[:, 128:129]) and np.all(RL[:, 144:160] == RL[:, 144:145])
+    assert RL[:, 128:].max() <= 205
+    QL, off, _ = synth.gen_queries(cfg, loc=True)
+    Q, off2, _ = synth.gen_queries(cfg)
+    assert np.array_equal(QL[:, :128], Q) and np.array_equal(off, off2)
+    a, b = QL[:40].astype(np.int64), RL[:40].astype(np.int64)
+    d160 = np.sum((a - b) ** 2, axis=1)
+    d128 = np.sum((a[:, :128] - b[:, :128]) ** 2, axis=1)
+    dc = (a[:, 128] - b[:, 128]) ** 2 + (a[:, 144] - b[:, 144]) ** 2
+    assert np.array_equal(d160, d128 + 16 * dc)
+    # the coding: 16 dcode^2 = (alpha * 512 * dcoord)^2 up to the rounding of
+    # each code (|code - 204.8 x| <= 1/2)
+    xy = np.array([[0.0, 1.0], [0.25, 0.5], [1.0, 0.0]])
+    codes = synth.loc_code(xy).astype(np.int64)
+    assert codes.tolist() == [[0, 205], [51, 102], [205, 0]]
+    dcode = codes[0] - codes[2]
+    want = (1.6 * 512 * (xy[0] - xy[2])) ** 2
+    assert np.all(np.abs(16 * dcode ** 2 - want) <= 16 * (2 * np.abs(dcode) + 1))
+    # prototype descriptors sit near their class's location centres
+    cen = synth.loc_centres(cfg)
+    assert cen.shape == (4, cfg.n_proto, 2) and cen.min() >= 0.15 and cen.max() <= 0.85
