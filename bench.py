@@ -182,6 +182,43 @@ def exact_leg(args, L, torch, np, synth):
     return res, ix, R, Q, cfg
 
 
+def loc_leg(args, L, torch, np, synth):
+    """The exact path on location-augmented rows at L's sizes: 160 u8 bytes
+    per descriptor (the descriptor, then 16 copies of each coordinate code
+    carrying the location weight alpha = 1.6), INT8 mode."""
+    cfg = synth.CONFIGS["L"]
+    t0 = time.perf_counter()
+    R, labels = synth.gen_index(cfg, loc=True)
+    Q, off, true_cls = synth.gen_queries(cfg, loc=True)
+    log(f"generated {R.shape[0]} x {R.shape[1]} location-augmented refs, {Q.shape[0]} queries "
+        f"in {time.perf_counter() - t0:.1f}s")
+    I8 = L.LNBNN_EXACT_I8
+    ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(I8))
+    del R
+    try:
+        dq = torch.from_numpy(Q).cuda()
+        tuned = os.path.exists(TUNING_CACHE)
+        if tuned:
+            L.lnbnn_autotune(ix, dq, off, args.k, I8, cache_path=TUNING_CACHE)
+        steps = max(1, min(args.steps, 3))
+        dt, k1_ms, timing, cls = time_exact(args, L, torch, np, ix, dq, off, cfg.n_classes, I8, steps, 1)
+    finally:
+        ix.free()
+    n_q = int(Q.shape[0])
+    ops = 2.0 * synth.DIM_LOC * cfg.n_refs * n_q
+    a = ops / (k1_ms / 1e3) / 1e12
+    return {"value": n_q / dt, "unit": "query descriptors/s", "steps": steps, "ms_per_step": dt * 1e3,
+            "dtype": "i8",
+            "config": {"workload": "L with location-augmented rows: 15.36M refs x 160 u8 (descriptor "
+                                   "+ 16 copies of each alpha-weighted coordinate code); 512 query "
+                                   f"images ({n_q} descriptors); k={args.k}; exact, INT8 matrix cores",
+                       "variant": L.lnbnn_variant_name(timing["tile_variant"]), "autotuned": tuned},
+            "roofline": {"bound": "mfma", "achieved": a, "peak": PEAK_MFMA_I8_TOPS, "unit": "TOP/s",
+                         "frac": a / PEAK_MFMA_I8_TOPS, "kernel": "k_dist_topk<OpI8L, 11, ...>",
+                         "kernel_ms": k1_ms, "algorithmic_ops_per_launch": ops},
+            "accuracy_statistic": float(np.mean(cls == true_cls))}
+
+
 def fp8_leg(args, L, torch, np, synth):
     """FP8 candidate pass (4k) + exact FP32 re-rank on float descriptors with
     config L's structure; recall of the k+1 neighbours on sampled descriptors
@@ -379,8 +416,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--k", type=int, default=10)
-    ap.add_argument("--legs", default="exact,fp8,serving,sweep",
-                    help="comma list: exact (always), fp8, serving, sweep")
+    ap.add_argument("--legs", default="exact,fp8,serving,sweep,loc",
+                    help="comma list: exact (always), fp8, serving, sweep, loc")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -429,6 +466,11 @@ def main():
             res["class_sweep"] = class_sweep_leg(args, L, torch, np, synth)
         except Exception as e:
             res["class_sweep"] = {"error": repr(e)}
+    if "loc" in legs:
+        try:
+            res["location_augmented"] = loc_leg(args, L, torch, np, synth)
+        except Exception as e:
+            res["location_augmented"] = {"error": repr(e)}
     print(json.dumps(res))
 
 

@@ -3,6 +3,7 @@ synthetic workload of a named shape and record the fastest in a tuning
 cache (flat JSON, key = arch, n_refs, dim, list-length bucket, mode).
 
     python -m paper_1112_0059_amd.tune --config L --mode f16 --k 10 --cache out.json
+    python -m paper_1112_0059_amd.tune --config L --mode i8 --loc --k 10 --cache out.json
 
 A later lnbnn_autotune call with the same cache and an index of the same
 shape pins the recorded variant without timing anything.
@@ -24,6 +25,7 @@ def main(argv=None):
     ap.add_argument("--k", type=int, nargs="+", default=[10])
     ap.add_argument("--images", type=int, default=0, help="query images to time on (0 = all)")
     ap.add_argument("--cache", required=True)
+    ap.add_argument("--loc", action="store_true", help="location-augmented 160-byte rows (INT8 mode)")
     args = ap.parse_args(argv)
 
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
@@ -37,8 +39,10 @@ def main(argv=None):
     if (mode == L.LNBNN_FP8_RERANK) != (cfg.kind == "f32"):
         sys.exit(f"config {args.config} holds {cfg.kind} descriptors; mode {args.mode} needs "
                  f"{'f32' if mode == L.LNBNN_FP8_RERANK else 'u8'}")
-    R, labels = synth.gen_index(cfg)
-    Q, off, _ = synth.gen_queries(cfg)
+    if args.loc and mode != L.LNBNN_EXACT_I8:
+        sys.exit("--loc needs --mode i8")
+    R, labels = synth.gen_index(cfg, loc=args.loc)
+    Q, off, _ = synth.gen_queries(cfg, loc=args.loc)
     if args.images:
         off = off[:args.images + 1]
         Q = Q[:off[-1]]
@@ -49,7 +53,7 @@ def main(argv=None):
         for k in args.k:
             t0 = time.perf_counter()
             v = L.lnbnn_autotune(ix, dq, off, k, mode, cache_path=args.cache)
-            print(f"{args.config} mode={args.mode} k={k}: variant {v} ({L.lnbnn_variant_name(v)}) "
+            print(f"{args.config}{' loc' if args.loc else ''} mode={args.mode} k={k}: variant {v} ({L.lnbnn_variant_name(v)}) "
                   f"in {time.perf_counter() - t0:.1f} s", flush=True)
     finally:
         ix.free()
