@@ -163,7 +163,7 @@ def exact_leg(args, L, torch, np, synth):
                    "slices": timing["slices"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_I8_TOPS,
                      "unit": "TOP/s", "frac": achieved / PEAK_MFMA_I8_TOPS,
-                     "traffic": traffic_per_launch(), "kernel": "k_dist_topk<OpI8, 11, ...>",
+                     "traffic": traffic_per_launch(), "kernel": "k_dist_topk<OpI8T<4, FMT_I8>, 11, ...>",
                      "kernel_ms": k1_ms, "algorithmic_ops_per_launch": flop},
         "accuracy_statistic": float(np.mean(cls == true_cls)),
     }
@@ -214,7 +214,7 @@ def loc_leg(args, L, torch, np, synth):
                                    f"images ({n_q} descriptors); k={args.k}; exact, INT8 matrix cores",
                        "variant": L.lnbnn_variant_name(timing["tile_variant"]), "autotuned": tuned},
             "roofline": {"bound": "mfma", "achieved": a, "peak": PEAK_MFMA_I8_TOPS, "unit": "TOP/s",
-                         "frac": a / PEAK_MFMA_I8_TOPS, "kernel": "k_dist_topk<OpI8L, 11, ...>",
+                         "frac": a / PEAK_MFMA_I8_TOPS, "kernel": "k_dist_topk<OpI8T<5, FMT_I8L>, 11, ...>",
                          "kernel_ms": k1_ms, "algorithmic_ops_per_launch": ops},
             "accuracy_statistic": float(np.mean(cls == true_cls))}
 
