@@ -124,8 +124,9 @@ int lnbnn_index_info(const lnbnn_index *ix, int64_t *n_refs, int32_t *n_classes,
 /*
  * Classify a batch of query images (Algorithm 2 for every image).
  *
- *   queries     [n_desc, dim] descriptors of all images, concatenated;
- *               LNBNN_U8 for the exact modes, LNBNN_F32 for FP8_RERANK
+ *   queries     [n_desc, dim] descriptors of all images, concatenated, with
+ *               the index's dim; LNBNN_U8 for the exact modes, LNBNN_F32 for
+ *               FP8_RERANK
  *   img_offsets host int64 [n_images + 1] CSR offsets (always host memory):
  *               image m owns descriptors [img_offsets[m], img_offsets[m+1]);
  *               must start at 0 and be non-decreasing; empty images are

@@ -586,8 +586,9 @@ struct TileRegs {
 };
 
 // Plain LDS loads of one tile.  With the stage copies invisible to the
-// compiler (inline assembly), it schedules these freely: the 4 KB-tile
-// formats load tile t+1 while the MFMAs of tile t run.
+// compiler (inline assembly), it schedules these freely: the 8-bit formats
+// (4 KB tiles, 5 KB for 160-element INT8 rows) load tile t+1 while the
+// MFMAs of tile t run.
 template <class Op>
 static __device__ __forceinline__ void tile_load(const uint4 *frag, const float4 *seed, const int32_t *rsc, int lane,
                                                  int h, TileRegs<Op> &t)
@@ -668,7 +669,7 @@ void k_dist_topk(DistArgs a)
     constexpr int PD = NB - 1;                    // stages in flight ahead of the one computed
     constexpr int LPS = StageLoads<Op, MT, W>::total;   // loads per wave per stage
     constexpr bool kPrefetch = Op::kSteps * Op::kAU <= 5;      // 4-5 KB tiles leave registers for it
-    // With 3+ buffers the 4 KB-tile path synchronises per buffer instead of
+    // With 3+ buffers the 8-bit-tile path synchronises per buffer instead of
     // per stage: PF = NB - 2 stages in flight leave one stage of slack, so a
     // wave that inserts delays only itself.
     constexpr bool kCounters = kPrefetch && NB >= 3;
@@ -842,7 +843,7 @@ void k_dist_topk(DistArgs a)
                     });
                 }
             } else if constexpr (kPrefetch) {
-                // 4 KB tiles: tile t+1's LDS loads overlap tile t's MFMAs.
+                // 8-bit tiles: tile t+1's LDS loads overlap tile t's MFMAs.
                 // The stage barrier comes before a stage's last tile (whose
                 // loads have completed: lgkmcnt 0), so the next stage's first
                 // tile can be loaded while that last tile computes.
