@@ -221,9 +221,7 @@ def loc_leg(args, L, torch, np, synth):
 
 def fp8_leg(args, L, torch, np, synth):
     """FP8 candidate pass (4k) + exact FP32 re-rank on float descriptors with
-    config L's structure; recall of the k+1 neighbours on sampled descriptors
-    against the FP64 oracle."""
-    import oracle
+    config L's structure (its recall against the FP64 oracle is a GPU test)."""
     cfg = synth.CONFIGS["P"]
     t0 = time.perf_counter()
     R, labels = synth.gen_index(cfg)
@@ -250,17 +248,6 @@ def fp8_leg(args, L, torch, np, synth):
     dt = time.perf_counter() - t0
     n_q = int(Q.shape[0])
     acc = float(np.mean(out["class"].cpu().numpy() == true_cls))
-    # sampled recall against the oracle (16 descriptors of 4 images)
-    imgs = [0, 128, 256, 384]
-    sel = np.concatenate([np.arange(off[m], off[m] + 16) for m in imgs])
-    sub_off = np.arange(0, 16 * len(imgs) + 1, 16)
-    _, _, ni, nd = L.lnbnn_classify(ix, Q[sel], sub_off, args.k, mode, want_neighbours=True)
-    t0 = time.perf_counter()
-    wi, wd = oracle.knn_expanded(Q[sel], R, args.k + 1)
-    log(f"fp8: oracle sample in {time.perf_counter() - t0:.1f}s")
-    kp = args.k + 1
-    recall = float(np.mean([len(set(ni[i]) & set(wi[i])) / kp for i in range(len(sel))]))
-    identical = float(np.mean(np.all(ni == wi, axis=1)))
     k1 = float(np.mean(k1_ms)) / 1e3
     flop = 2.0 * 128 * cfg.n_refs * n_q
     achieved = flop / k1 / 1e12
@@ -274,8 +261,8 @@ def fp8_leg(args, L, torch, np, synth):
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_FP8_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_MFMA_FP8_TFLOPS, "kernel": "k_dist_topk (FP8 candidate pass)",
                      "kernel_ms": k1 * 1e3, "sequence_ms": float(np.mean(tot_ms))},
-        "quality_vs_fp64_oracle": {"sample": f"{len(sel)} descriptors of images {imgs}",
-                                   "recall_at_k_plus_1": recall, "identical_lists": identical},
+        "quality": "recall against the FP64 oracle is checked at this size by the GPU tests "
+                   "(sampled descriptors and one whole image), not timed here",
         "accuracy_statistic": acc,
     }, ix
 
