@@ -1,5 +1,6 @@
 """Full-size checks at the benchmarked workloads, in the launch configuration
-the benchmark times (device pointers, one batched launch sequence).
+the benchmark times (device pointers, one batched launch sequence, the tile
+variant and chunk walk the committed tuning cache pins for the workload).
 
 Exact path, 15.36M references, 512 query images, k = 10 (INT8 mode):
   * every returned neighbour carries its exact squared distance and every
@@ -13,7 +14,10 @@ FP8 + re-rank, float descriptors of the same shape:
     rounding bound, lists in (distance, index) order;
   * sampled descriptors' recall and one whole image's decision against the
     FP64 oracle.
+Location-augmented rows (160 bytes), INT8 mode, L's sizes: the same three
+exact checks as the 128-byte exact path.
 """
+import os
 import sys
 
 import numpy as np
@@ -25,6 +29,15 @@ import synth
 
 pytestmark = pytest.mark.gpu
 GAMMA = 130 * 2.0 ** -24
+CACHE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                     "paper_1112_0059_amd", "tuning_cache.json")
+
+
+def _bench_launch(ix, dq, off, k, mode):
+    """Pin the tuned launch the benchmark uses (a cache hit times nothing)."""
+    v = L.lnbnn_autotune(ix, dq, off, k, mode, cache_path=CACHE)
+    _say(f"launch configuration: variant {L.lnbnn_variant_name(v)}")
+    return v
 
 
 def _say(*a):
@@ -64,6 +77,7 @@ def big():
     Q, off, true_cls = synth.gen_queries(cfg)
     ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(L.LNBNN_EXACT_I8))
     dq = torch.from_numpy(Q).cuda()
+    _bench_launch(ix, dq, off, 10, L.LNBNN_EXACT_I8)
     _say("classifying 512 images")
     cls, tot, ni, nd = L.lnbnn_classify(ix, dq, off, 10, L.LNBNN_EXACT_I8, want_neighbours=True)
     torch.cuda.synchronize()
@@ -148,6 +162,7 @@ def bigf():
     Q, off, true_cls = synth.gen_queries(cfg)
     ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(L.LNBNN_FP8_RERANK))
     dq = torch.from_numpy(Q).cuda()
+    _bench_launch(ix, dq, off, 10, L.LNBNN_FP8_RERANK)
     _say("classifying 512 float images")
     cls, tot, ni, nd = L.lnbnn_classify(ix, dq, off, 10, L.LNBNN_FP8_RERANK, want_neighbours=True)
     torch.cuda.synchronize()
@@ -194,3 +209,49 @@ def test_full_fp8_sampled_against_oracle(bigf):
     _say(f"score error {err:.3e} (oracle top-2 margin {margin:.3e})")
     if np.all(same):
         assert err <= GAMMA * 2 * np.abs(wt[0]).sum() + 1e-9
+
+
+@pytest.fixture(scope="module")
+def bigloc():
+    import torch
+    cfg = synth.CONFIGS["L"]
+    _say("generating the 15.36M x 160 location-augmented index")
+    R, labels = synth.gen_index(cfg, loc=True)
+    Q, off, _ = synth.gen_queries(cfg, loc=True)
+    ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(L.LNBNN_EXACT_I8))
+    dq = torch.from_numpy(Q).cuda()
+    _bench_launch(ix, dq, off, 10, L.LNBNN_EXACT_I8)
+    _say("classifying 512 location-augmented images")
+    cls, tot, ni, nd = L.lnbnn_classify(ix, dq, off, 10, L.LNBNN_EXACT_I8, want_neighbours=True)
+    torch.cuda.synchronize()
+    got = (cls.cpu().numpy(), tot.cpu().numpy(), ni.cpu().numpy(), nd.cpu().numpy())
+    yield cfg, R, labels, Q, off, got
+    ix.free()
+
+
+@pytest.mark.timeout(900)
+def test_full_loc_exact(bigloc):
+    """Every list holds exact 160-element squared distances in (distance,
+    index) order, the totals and classes follow from the lists, and 64
+    sampled descriptors plus the smallest whole image equal the oracle."""
+    cfg, R, labels, Q, off, (cls, tot, ni, nd) = bigloc
+    assert ni.shape == (Q.shape[0], 11) and ni.min() >= 0 and ni.max() < cfg.n_refs
+    assert _sorted_lists(ni, nd)
+    _say("recomputing 12.7M neighbour distances over 160 elements")
+    for s in range(0, Q.shape[0], 1 << 15):
+        q = Q[s:s + (1 << 15)].astype(np.int32)
+        r = R[ni[s:s + (1 << 15)]].astype(np.int32)
+        d = np.sum((r - q[:, None, :]) ** 2, axis=2)
+        assert np.array_equal(d, nd[s:s + (1 << 15)].astype(np.int64)), s
+    T = _totals_from_lists(ni, nd, labels, cfg.n_classes, off, 10)
+    assert np.array_equal(T, tot) and np.array_equal(np.argmin(tot, axis=1), cls)
+    imgs = [3, 200, 377, 511]
+    sel = np.concatenate([np.arange(off[m], off[m] + 16) for m in imgs])
+    _say("oracle kNN for 64 sampled location-augmented descriptors")
+    wi, wd = oracle.knn_expanded(Q[sel], R, 11)
+    assert np.array_equal(ni[sel], wi) and np.array_equal(nd[sel].astype(np.int64), wd)
+    m = int(np.argmin(np.diff(off)))
+    s, e = int(off[m]), int(off[m + 1])
+    _say(f"oracle classification of image {m} ({e - s} descriptors)")
+    wt, wc, _, _ = oracle.classify(Q[s:e], R, labels, cfg.n_classes, np.array([0, e - s]), 10)
+    assert np.array_equal(tot[m], wt[0]) and cls[m] == wc[0]
