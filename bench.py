@@ -233,6 +233,10 @@ def fp8_leg(args, L, torch, np, synth):
     out = {"class": torch.empty(n_img, dtype=torch.int32, device="cuda"),
            "totals": torch.empty((n_img, cfg.n_classes), dtype=torch.float64, device="cuda")}
     mode = L.LNBNN_FP8_RERANK
+    tuned = os.path.exists(TUNING_CACHE)
+    if tuned:
+        # the tuned launch for this workload (a cache hit times nothing)
+        L.lnbnn_autotune(ix, dq, off, args.k, mode, cache_path=TUNING_CACHE)
     L.lnbnn_classify(ix, dq, off, args.k, mode, flags=L.LNBNN_TIMING, out=out)
     torch.cuda.synchronize()
     steps = max(1, min(args.steps, 3))
@@ -257,7 +261,9 @@ def fp8_leg(args, L, torch, np, synth):
         "value": n_q * steps / dt, "unit": "query descriptors/s", "steps": steps,
         "ms_per_step": dt / steps * 1e3, "dtype": "fp8 e4m3 -> f32",
         "config": {"workload": "P: 15.36M float32 refs (L structure, unit-norm ReLU descriptors, noise 0.08), "
-                               f"{n_q} query descriptors in 512 images; k={args.k}, 4k candidates"},
+                               f"{n_q} query descriptors in 512 images; k={args.k}, 4k candidates",
+                   "variant": L.lnbnn_variant_name(L.lnbnn_last_timing(ix)["tile_variant"]),
+                   "autotuned": tuned},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_FP8_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_MFMA_FP8_TFLOPS, "kernel": "k_dist_topk (FP8 candidate pass)",
                      "kernel_ms": k1 * 1e3, "sequence_ms": float(np.mean(tot_ms))},
