@@ -97,3 +97,43 @@ def test_variants_listed():
     names = [L.lnbnn_variant_name(v) for v in range(n)]
     assert len(set(names)) == n and "?" not in names
     assert L.lnbnn_variant_name(n) == "?"
+
+
+def test_tuning_cache_entries_decode():
+    """Every committed tuning-cache value decodes to a built variant and a
+    chunk length the kernel accepts (a multiple of 8 tiles, 0 = whole
+    slice); 160-byte rows use a 5 KB-tile stage shape."""
+    import json
+    with open(os.path.join(ROOT, "paper_1112_0059_amd", "tuning_cache.json")) as f:
+        cache = json.load(f)
+    assert cache
+    n = L.lnbnn_num_variants()
+    loc_shapes = {"w4_nt2_mt4_nb2", "w4_nt2_mt4_nb3", "w8_nt2_mt8_nb3", "w8_nt1_mt8_nb3"}
+    for key, val in cache.items():
+        fields = dict(kv.split("=") for kv in key.split(","))
+        assert set(fields) == {"arch", "n_refs", "dim", "kp", "mode"}, key
+        v, chunk = val & 0xFF, val >> 8
+        assert 0 <= v < n and chunk >= 0 and chunk % 8 == 0, key
+        if fields["dim"] == str(L.LNBNN_DIM_LOC):
+            assert fields["mode"] == str(L.LNBNN_EXACT_I8) and L.lnbnn_variant_name(v) in loc_shapes, key
+
+
+def test_query_width_checked_before_any_call():
+    """The binding rejects queries whose width is not the index's before it
+    calls into the library (no device needed)."""
+    ix = L.Index(None, 100, 3, 0, L.LNBNN_DIM_LOC)
+    off = np.array([0, 3], np.int64)
+    with pytest.raises(L.LnbnnError):
+        L.lnbnn_classify(ix, np.zeros((3, 128), np.uint8), off, 5, L.LNBNN_EXACT_I8)
+    with pytest.raises(L.LnbnnError):
+        L.lnbnn_submit(ix, np.zeros((3, 128), np.uint8), 5, L.LNBNN_EXACT_I8)
+    ix.handle = None
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout
