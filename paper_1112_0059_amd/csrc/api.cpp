@@ -111,6 +111,17 @@ void drop_graphs(std::map<std::string, GraphEntry> &graphs)
 
 static void drop_graphs(lnbnn_index *ix) { drop_graphs(ix->graphs); }
 
+// Wait for the work that may still use a workspace before its buffers are
+// replaced: the index's own workspace is last used by the work before the
+// ws_free event; a serving slot's grows only when the slot is created, with
+// no work on it yet.  (No device-wide synchronisation: another thread may be
+// capturing a graph on a serving stream, and that call is refused then.)
+static int quiesce_ws(lnbnn_index *ix, const Workspace &ws)
+{
+    if (&ws == &ix->ws && ix->ws_used) LN_HIP(hipEventSynchronize(ix->ws_free));
+    return LNBNN_OK;
+}
+
 int ensure_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int64_t img_cap, int64_t part, int64_t nbr,
               int64_t qbytes, bool need_f64)
 {
@@ -118,11 +129,11 @@ int ensure_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int64_t img_cap, in
                     nbr <= ws.nbr_cap && qbytes <= ws.qbytes_cap && (!need_f64 || ws.totals_f64);
     if (ok && ws.bd) return LNBNN_OK;
     // buffers may be in use by earlier asynchronous work
-    LN_HIP(hipDeviceSynchronize());
+    int rc;
+    if ((rc = quiesce_ws(ix, ws))) return rc;
     if (&ws == &ix->ws) drop_graphs(ix);
     const int64_t nc = ix->n_classes;
     img_cap = std::max(img_cap, ws.img_cap);
-    int rc;
     if (img_cap > ws.img_cap || !ws.bd) {
         if ((rc = grow((void **)&ws.offsets, 0, 2 * img_cap + 2, 8))) return rc;
         if ((rc = grow((void **)&ws.bd, 0, img_cap + 1, sizeof(BatchDesc)))) return rc;
@@ -156,9 +167,9 @@ int ensure_fp8_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int n_cand, int
 {
     const int64_t cand = q_cap * n_cand, upd = q_cap * k;
     if (q_cap <= ws.q8_cap && cand <= ws.cand_cap && upd <= ws.upd_cap && ws.q8) return LNBNN_OK;
-    LN_HIP(hipDeviceSynchronize());
-    if (&ws == &ix->ws) drop_graphs(ix);
     int rc;
+    if ((rc = quiesce_ws(ix, ws))) return rc;
+    if (&ws == &ix->ws) drop_graphs(ix);
     if (q_cap > ws.q8_cap || !ws.q8) {
         if ((rc = grow((void **)&ws.q8, 0, q_cap * (kDim / 16), 16))) return rc;
         if ((rc = grow((void **)&ws.qsc, 0, q_cap, 4))) return rc;
@@ -526,9 +537,12 @@ extern "C" int lnbnn_index_free(lnbnn_index *ix)
 {
     if (!ix) return LNBNN_OK;
     if (server_pending(ix)) return set_err(LNBNN_EBUSY, "index has pending tickets");
-    server_stop(ix);
+    server_stop(ix);                       // joins the serving threads after their streams drain
     (void)hipSetDevice(ix->device);
-    (void)hipDeviceSynchronize();
+    // the index's own work: classify calls (up to the ws_free event) and
+    // its stream
+    if (ix->ws_used) (void)hipEventSynchronize(ix->ws_free);
+    if (ix->own_stream) (void)hipStreamSynchronize(ix->own_stream);
     drop_graphs(ix);
     free_index_buffers(ix);
     for (auto &e : ix->tev)
@@ -725,6 +739,19 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
 
     // the shared workspace may still be read by a call on another stream
     if (ix->ws_used) LN_HIP(hipStreamWaitEvent(s, ix->ws_free, 0));
+    // from here on, every exit (errors included) marks the end of this
+    // call's use of the workspace on `s`
+    struct WsFence {
+        lnbnn_index *ix;
+        hipStream_t s;
+        bool armed;
+        ~WsFence()
+        {
+            if (!armed) return;
+            (void)hipEventRecord(ix->ws_free, s);
+            ix->ws_used = true;
+        }
+    } fence{ix, s, true};
     const void *dq = queries;
     if (!dev && n_q > 0) {
         LN_HIP(hipMemcpyAsync(ws.q, queries, (size_t)(n_q * rb), hipMemcpyHostToDevice, s));
@@ -788,6 +815,7 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
             LN_HIP(hipMemcpyAsync(out_nbr_dist, ws.nbr_dist, (size_t)(n_q * kp * 4), hipMemcpyDeviceToHost, s));
         }
     }
+    fence.armed = false;
     LN_HIP(hipEventRecord(ix->ws_free, s));
     ix->ws_used = true;
     if (!dev) LN_HIP(hipStreamSynchronize(s));

@@ -125,17 +125,38 @@ def test_serving_busy_and_injected_failure():
             ix.free()
 
 
-def test_serving_fp8_matches_classify():
+@pytest.mark.parametrize("k", [10, 32])
+def test_serving_fp8_matches_classify(k):
+    """FP8 requests through the serving loop equal the batched classify,
+    up to the largest k (64-entry candidate lists, 128 re-ranked)."""
     cfg = synth.scaled(synth.CONFIGS["P"], n_classes=6, n_train=3, n_desc=300, n_img=10, q_lo=100, q_hi=400,
                        index_seed=5100, query_seed=6100)
     R, labels = synth.gen_index(cfg)
     Q, off, _ = synth.gen_queries(cfg)
     ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(L.LNBNN_FP8_RERANK))
     try:
-        tickets = [L.lnbnn_submit(ix, Q[off[i]:off[i + 1]], 10, L.LNBNN_FP8_RERANK) for i in range(10)]
-        batch = L.lnbnn_classify(ix, Q, off, 10, L.LNBNN_FP8_RERANK)
+        tickets = [L.lnbnn_submit(ix, Q[off[i]:off[i + 1]], k, L.LNBNN_FP8_RERANK) for i in range(10)]
+        batch = L.lnbnn_classify(ix, Q, off, k, L.LNBNN_FP8_RERANK)
         for i, t in enumerate(tickets):
             c, tot, _ = _wait(ix, t)
             assert c == batch[0][i] and np.array_equal(tot, batch[1][i])
+    finally:
+        ix.free()
+
+
+def test_serving_exact_k32_matches_classify():
+    """Exact requests at the largest k through the serving loop equal the
+    batched classify and the oracle."""
+    cfg = synth.scaled(synth.CONFIGS["T"], n_img=8, q_lo=50, q_hi=300)
+    R, labels = synth.gen_index(cfg)
+    Q, off, _ = synth.gen_queries(cfg)
+    I8 = L.LNBNN_EXACT_I8
+    ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(I8))
+    try:
+        tickets = [L.lnbnn_submit(ix, Q[off[i]:off[i + 1]], 32, I8) for i in range(8)]
+        want_t, want_c, _, _ = oracle.classify(Q, R, labels, cfg.n_classes, off, 32)
+        for i, t in enumerate(tickets):
+            c, tot, _ = _wait(ix, t)
+            assert c == want_c[i] and np.array_equal(tot, want_t[i])
     finally:
         ix.free()
