@@ -10,8 +10,10 @@ Two kinds of routes:
 
 * the C library ``liblnbnn_oracle.so`` (built from ``lnbnn_oracle.c``):
   direct-form distances in int64 (u8) or double (f32), k+1 nearest by a full
-  sort or by a single insertion scan, Algorithm 2 as printed, Algorithm 1,
-  and the closed form of Algorithm 2's totals;
+  sort, by a single insertion scan, or by the same scan tiled for the cache
+  (route "block", used for whole-image checks at full index size),
+  Algorithm 2 as printed, Algorithm 1, and the closed form of Algorithm 2's
+  totals;
 * ``knn_expanded``: a numpy route for larger sampled checks.  It evaluates
   ||q||^2 + ||r||^2 - 2 q.r with a float64 matrix product, which is exact
   for u8 descriptors (every partial sum is an integer below 2^53), and
@@ -39,11 +41,14 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile the C oracle with gcc (portable -O2, OpenMP)."""
+    """Compile the C oracle with gcc (OpenMP; ISO C, so no multiply-add
+    contraction: every double operation is rounded as written).  The blocked
+    route is compiled for several x86 vector widths and picked at load time;
+    the arithmetic is the same IEEE operations on every width."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC",
-               "-Wall", "-Wextra", _SRC, "-o", tmp, "-lm"]
+        cmd = ["gcc", "-O3", "-std=c11", "-ffp-contract=off", "-fopenmp", "-shared",
+               "-fPIC", "-Wall", "-Wextra", _SRC, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -66,6 +71,8 @@ def _load():
         "or_knn_u8_scan": ([P, i64, P, i64, i32, i32, P, P], ctypes.c_int),
         "or_knn_f32_sort": ([P, i64, P, i64, i32, i32, P, P], ctypes.c_int),
         "or_knn_f32_scan": ([P, i64, P, i64, i32, i32, P, P], ctypes.c_int),
+        "or_knn_u8_block": ([P, i64, P, i64, i32, i32, P, i32, P, P, P], ctypes.c_int),
+        "or_knn_f32_block": ([P, i64, P, i64, i32, i32, P, P], ctypes.c_int),
         "or_local_nbnn_i64": ([P, P, i64, i32, P, i32, P, i32, P, P], ctypes.c_int),
         "or_local_nbnn_f64": ([P, P, i64, i32, P, i32, P, i32, P, P], ctypes.c_int),
         "or_class_nn_u8": ([P, i64, P, i64, i32, P, i32, i32, P, P], ctypes.c_int),
@@ -128,6 +135,15 @@ def knn(Q, R, kp: int, route: str = "scan"):
     assert R.shape[1] == dim
     idx = np.empty((n, kp), np.int32)
     dist = np.empty((n, kp), np.int64 if is_u8 else np.float64)
+    if route == "block":
+        if is_u8:
+            rc = lib.or_knn_u8_block(_p(Q), n, _p(R), N, dim, kp, None, 0,
+                                     _p(idx), _p(dist), None)
+        else:
+            rc = lib.or_knn_f32_block(_p(Q), n, _p(R), N, dim, kp, _p(idx), _p(dist))
+        if rc != 0:
+            raise ValueError("oracle knn failed (kp > N or out of memory)")
+        return idx, dist
     fn = {("u8", "sort"): lib.or_knn_u8_sort, ("u8", "scan"): lib.or_knn_u8_scan,
           ("f32", "sort"): lib.or_knn_f32_sort, ("f32", "scan"): lib.or_knn_f32_scan}[
         ("u8" if is_u8 else "f32", route)]
@@ -240,6 +256,25 @@ def class_nn(Q, R, labels, n_classes: int, k: int):
     if rc != 0:
         raise ValueError("invalid arguments to class_nn")
     return D, kth
+
+
+def knn_class_block(Q, R, labels, n_classes: int, kp: int):
+    """u8 descriptors, one blocked pass: the kp nearest (distance, index)
+    pairs of every query (as ``knn``) and the per-class nearest distance
+    D[i, C] (as ``class_nn``; INT64_MAX for an empty class).  The (k+1)-th
+    smallest distance that ``class_nn`` returns is ``dist[:, kp - 1]``."""
+    lib = _load()
+    Q, R = _c(Q, np.uint8), _c(R, np.uint8)
+    labels = _c(labels, np.int32)
+    n, dim = Q.shape
+    idx = np.empty((n, kp), np.int32)
+    dist = np.empty((n, kp), np.int64)
+    D = np.empty((n, n_classes), np.int64)
+    rc = lib.or_knn_u8_block(_p(Q), n, _p(R), R.shape[0], dim, kp, _p(labels), n_classes,
+                             _p(idx), _p(dist), _p(D))
+    if rc != 0:
+        raise ValueError("invalid arguments to knn_class_block")
+    return idx, dist, D
 
 
 def closed_form(D, kth, offsets):

@@ -19,7 +19,8 @@
  *   - integer (u8) descriptors use exact int64 arithmetic; float descriptors
  *     are widened to double and use the direct form sum_t (q_t - r_t)^2.
  *
- * Parallelism: OpenMP over query descriptors for the distance scans only;
+ * Parallelism: OpenMP over query descriptors (or blocks of them) for the
+ * distance scans only;
  * every reduction into per-image totals runs serially per image in
  * descriptor order, then neighbour order, so float totals are reproducible.
  */
@@ -239,6 +240,241 @@ int or_knn_f32_scan(const float *Q, int64_t n, const float *R, int64_t N,
                 out_dist[i * kp + p] = best[p].d;
             }
         }
+        free(best);
+    }
+    return err;
+}
+
+/* ------------------------------------------------------------------ */
+/* Route "block": the scan route, tiled for the cache                  */
+/* ------------------------------------------------------------------ */
+/*
+ * Same per-pair arithmetic as or_sqdist_u8 / or_sqdist_f32 (direct form,
+ * summed in dimension order) and the same insertion rule as the scan
+ * route, so the lists are identical to the scan and sort routes'.  Only
+ * the loop order differs: a thread takes a block of OR_QB queries and
+ * walks the references in groups of OR_JB; each group is widened and
+ * transposed once into a small buffer and then compared with every query
+ * of the block, OR_JB references at a time, so a group is read from memory
+ * once per block instead of once per query.  The per-reference distances of
+ * a group are independent sums, so each vector lane carries one reference's
+ * sum and no sum is reordered.
+ *
+ * u8 data is summed in int32: a squared difference is at most 255^2 and a
+ * row of at most 256 elements sums to less than 2^31, so the sums are exact
+ * (the same integers as the int64 routes).
+ */
+#define OR_QB 64   /* queries per block (a multiple of OR_NQ) */
+#define OR_JB 16   /* references per group */
+#define OR_NQ 4    /* queries that share each load of a group's column */
+
+typedef double or_vd8 __attribute__((vector_size(64)));     /* 8 doubles */
+typedef int32_t or_vi16 __attribute__((vector_size(64)));   /* 16 int32 */
+
+/* acc[i][jj] = sum over t = 0..dim-1, in that order, of (q_i[t] - r_jj[t])^2
+ * for the queries of a block (rows of qb; nq rounded up to OR_NQ, the extra
+ * rows are zeros) and the OR_JB references of a group, stored transposed:
+ * rt[t * OR_JB + jj].  Each vector lane holds one reference's running sum,
+ * so every sum is the sequential sum of or_sqdist_f32. */
+__attribute__((target_clones("avx512f", "avx2", "default")))
+static void group_f64(const double *qb, int32_t nq, const double *rt, int32_t dim,
+                      double *acc)
+{
+    for (int32_t i0 = 0; i0 < nq; i0 += OR_NQ) {
+        or_vd8 s[OR_NQ][2];
+        memset(s, 0, sizeof s);
+        for (int32_t t = 0; t < dim; ++t) {
+            or_vd8 r0, r1;
+            memcpy(&r0, rt + (int64_t)t * OR_JB, sizeof r0);
+            memcpy(&r1, rt + (int64_t)t * OR_JB + 8, sizeof r1);
+            for (int32_t u = 0; u < OR_NQ; ++u) {
+                const double qt = qb[(int64_t)(i0 + u) * dim + t];
+                or_vd8 d0 = qt - r0, d1 = qt - r1;
+                s[u][0] += d0 * d0;
+                s[u][1] += d1 * d1;
+            }
+        }
+        memcpy(acc + (int64_t)i0 * OR_JB, s, sizeof s);
+    }
+}
+
+/* The same for u8 data widened to int32 (exact: see above). */
+__attribute__((target_clones("avx512f", "avx2", "default")))
+static void group_i32(const int32_t *qb, int32_t nq, const int32_t *rt, int32_t dim,
+                      int32_t *acc)
+{
+    for (int32_t i0 = 0; i0 < nq; i0 += OR_NQ) {
+        or_vi16 s[OR_NQ];
+        memset(s, 0, sizeof s);
+        for (int32_t t = 0; t < dim; ++t) {
+            or_vi16 r;
+            memcpy(&r, rt + (int64_t)t * OR_JB, sizeof r);
+            for (int32_t u = 0; u < OR_NQ; ++u) {
+                or_vi16 d = qb[(int64_t)(i0 + u) * dim + t] - r;
+                s[u] += d * d;
+            }
+        }
+        memcpy(acc + (int64_t)i0 * OR_JB, s, sizeof s);
+    }
+}
+
+/* Insert candidate c into the sorted list best[0..filled) of capacity kp,
+ * exactly as the scan route does (strictly better than the kp-th entry). */
+static void list_insert_i64(pair_i64 *best, int32_t *filled, int32_t kp, pair_i64 c)
+{
+    if (*filled == kp && cmp_pair_i64(&c, &best[kp - 1]) >= 0) return;
+    int32_t pos = *filled < kp ? *filled : kp - 1;
+    while (pos > 0 && cmp_pair_i64(&c, &best[pos - 1]) < 0) {
+        best[pos] = best[pos - 1];
+        --pos;
+    }
+    best[pos] = c;
+    if (*filled < kp) ++*filled;
+}
+
+static void list_insert_f64(pair_f64 *best, int32_t *filled, int32_t kp, pair_f64 c)
+{
+    if (*filled == kp && cmp_pair_f64(&c, &best[kp - 1]) >= 0) return;
+    int32_t pos = *filled < kp ? *filled : kp - 1;
+    while (pos > 0 && cmp_pair_f64(&c, &best[pos - 1]) < 0) {
+        best[pos] = best[pos - 1];
+        --pos;
+    }
+    best[pos] = c;
+    if (*filled < kp) ++*filled;
+}
+
+/* u8 descriptors.  Either output may be left out:
+ *   out_idx/out_dist (both or neither): the kp nearest (distance, index)
+ *     pairs of every query, as or_knn_u8_scan;
+ *   D (with labels, n_classes): per-class nearest distance of every query,
+ *     as or_class_nn_u8 (INT64_MAX for a class with no reference).
+ * Returns 0, or -1 on bad arguments or a failed allocation. */
+int or_knn_u8_block(const uint8_t *Q, int64_t n, const uint8_t *R, int64_t N,
+                    int32_t dim, int32_t kp, const int32_t *labels, int32_t n_classes,
+                    int32_t *out_idx, int64_t *out_dist, int64_t *D)
+{
+    const int want_list = out_idx != NULL;
+    if (want_list && (kp < 1 || kp > N || out_dist == NULL)) return -1;
+    if (dim < 1 || dim > 256) return -1;
+    if (D != NULL) {
+        if (labels == NULL || n_classes < 1) return -1;
+        for (int64_t j = 0; j < N; ++j)
+            if (labels[j] < 0 || labels[j] >= n_classes) return -1;
+    }
+    const int64_t nblk = (n + OR_QB - 1) / OR_QB;
+    int err = 0;
+#pragma omp parallel
+    {
+        int32_t *qb = (int32_t *)malloc(sizeof(int32_t) * OR_QB * (size_t)dim);
+        int32_t *rt = (int32_t *)malloc(sizeof(int32_t) * OR_JB * (size_t)dim);
+        int32_t *acc = (int32_t *)malloc(sizeof(int32_t) * OR_QB * OR_JB);
+        pair_i64 *best = (pair_i64 *)malloc(sizeof(pair_i64) * OR_QB * (size_t)(kp > 0 ? kp : 1));
+        int32_t filled[OR_QB];
+        int ok = qb && rt && acc && best;
+        if (!ok) {
+#pragma omp atomic write
+            err = -1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t b = 0; b < nblk; ++b) {
+            if (!ok) continue;
+            const int64_t i0 = b * OR_QB;
+            const int32_t nq = (int32_t)(n - i0 < OR_QB ? n - i0 : OR_QB);
+            for (int32_t i = nq; i < OR_QB; ++i)
+                for (int32_t t = 0; t < dim; ++t) qb[i * dim + t] = 0;
+            for (int32_t i = 0; i < nq; ++i) {
+                for (int32_t t = 0; t < dim; ++t) qb[i * dim + t] = Q[(i0 + i) * dim + t];
+                filled[i] = 0;
+                if (D != NULL)
+                    for (int32_t c = 0; c < n_classes; ++c) D[(i0 + i) * n_classes + c] = INT64_MAX;
+            }
+            for (int64_t j0 = 0; j0 < N; j0 += OR_JB) {
+                const int32_t jb = (int32_t)(N - j0 < OR_JB ? N - j0 : OR_JB);
+                for (int32_t t = 0; t < dim; ++t)
+                    for (int32_t jj = 0; jj < OR_JB; ++jj)
+                        rt[t * OR_JB + jj] = jj < jb ? R[(j0 + jj) * dim + t] : 0;
+                group_i32(qb, nq, rt, dim, acc);
+                for (int32_t i = 0; i < nq; ++i)
+                    for (int32_t jj = 0; jj < jb; ++jj) {
+                        int64_t d = acc[i * OR_JB + jj];
+                        if (want_list) {
+                            pair_i64 c = { d, j0 + jj };
+                            list_insert_i64(best + (int64_t)i * kp, &filled[i], kp, c);
+                        }
+                        if (D != NULL) {
+                            int64_t *Dc = D + (i0 + i) * n_classes + labels[j0 + jj];
+                            if (d < *Dc) *Dc = d;
+                        }
+                    }
+            }
+            if (want_list)
+                for (int32_t i = 0; i < nq; ++i)
+                    for (int32_t p = 0; p < kp; ++p) {
+                        out_idx[(i0 + i) * kp + p] = (int32_t)best[i * kp + p].idx;
+                        out_dist[(i0 + i) * kp + p] = best[i * kp + p].d;
+                    }
+        }
+        free(qb);
+        free(rt);
+        free(acc);
+        free(best);
+    }
+    return err;
+}
+
+/* Float descriptors: the kp nearest (distance, index) pairs, double
+ * distances, as or_knn_f32_scan. */
+int or_knn_f32_block(const float *Q, int64_t n, const float *R, int64_t N,
+                     int32_t dim, int32_t kp, int32_t *out_idx, double *out_dist)
+{
+    if (kp < 1 || kp > N || dim < 1) return -1;
+    const int64_t nblk = (n + OR_QB - 1) / OR_QB;
+    int err = 0;
+#pragma omp parallel
+    {
+        double *qb = (double *)malloc(sizeof(double) * OR_QB * (size_t)dim);
+        double *rt = (double *)malloc(sizeof(double) * OR_JB * (size_t)dim);
+        double *acc = (double *)malloc(sizeof(double) * OR_QB * OR_JB);
+        pair_f64 *best = (pair_f64 *)malloc(sizeof(pair_f64) * OR_QB * (size_t)kp);
+        int32_t filled[OR_QB];
+        int ok = qb && rt && acc && best;
+        if (!ok) {
+#pragma omp atomic write
+            err = -1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t b = 0; b < nblk; ++b) {
+            if (!ok) continue;
+            const int64_t i0 = b * OR_QB;
+            const int32_t nq = (int32_t)(n - i0 < OR_QB ? n - i0 : OR_QB);
+            for (int32_t i = nq; i < OR_QB; ++i)
+                for (int32_t t = 0; t < dim; ++t) qb[i * dim + t] = 0.0;
+            for (int32_t i = 0; i < nq; ++i) {
+                for (int32_t t = 0; t < dim; ++t) qb[i * dim + t] = (double)Q[(i0 + i) * dim + t];
+                filled[i] = 0;
+            }
+            for (int64_t j0 = 0; j0 < N; j0 += OR_JB) {
+                const int32_t jb = (int32_t)(N - j0 < OR_JB ? N - j0 : OR_JB);
+                for (int32_t t = 0; t < dim; ++t)
+                    for (int32_t jj = 0; jj < OR_JB; ++jj)
+                        rt[t * OR_JB + jj] = jj < jb ? (double)R[(j0 + jj) * dim + t] : 0.0;
+                group_f64(qb, nq, rt, dim, acc);
+                for (int32_t i = 0; i < nq; ++i)
+                    for (int32_t jj = 0; jj < jb; ++jj) {
+                        pair_f64 c = { acc[i * OR_JB + jj], j0 + jj };
+                        list_insert_f64(best + (int64_t)i * kp, &filled[i], kp, c);
+                    }
+            }
+            for (int32_t i = 0; i < nq; ++i)
+                for (int32_t p = 0; p < kp; ++p) {
+                    out_idx[(i0 + i) * kp + p] = (int32_t)best[i * kp + p].idx;
+                    out_dist[(i0 + i) * kp + p] = best[i * kp + p].d;
+                }
+        }
+        free(qb);
+        free(rt);
+        free(acc);
         free(best);
     }
     return err;

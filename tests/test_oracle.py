@@ -36,7 +36,7 @@ def test_handworked_distances(hw):
         assert got == row
 
 
-@pytest.mark.parametrize("route", ["sort", "scan", "expanded"])
+@pytest.mark.parametrize("route", ["sort", "scan", "block", "expanded"])
 def test_handworked_neighbours(hw, route):
     R, Q = _u8(hw["refs"]), _u8(hw["queries"])
     for case in hw["cases"]:
@@ -104,8 +104,10 @@ def test_knn_routes_agree(seed):
         i1, d1 = oracle.knn(Q, R, kp, route="sort")
         i2, d2 = oracle.knn(Q, R, kp, route="scan")
         i3, d3 = oracle.knn_expanded(Q, R, kp, chunk=17)
+        i4, d4 = oracle.knn(Q, R, kp, route="block")
         assert np.array_equal(i1, i2) and np.array_equal(d1, d2)
         assert np.array_equal(i1, i3) and np.array_equal(d1, d3)
+        assert np.array_equal(i1, i4) and np.array_equal(d1, d4)
         # lexicographic (distance, index) order within each list
         assert np.all((np.diff(d1, axis=1) > 0) | ((np.diff(d1, axis=1) == 0) & (np.diff(i1, axis=1) > 0)))
 
@@ -116,11 +118,39 @@ def test_knn_against_full_enumeration():
     Q, R, _, _ = _case(11, n_refs=40, n_q=10)
     diff = Q[:, None, :].astype(np.int64) - R[None, :, :].astype(np.int64)
     full = np.sum(diff * diff, axis=2)
-    idx, dist = oracle.knn(Q, R, 7)
-    for i in range(Q.shape[0]):
-        order = np.lexsort((np.arange(R.shape[0]), full[i]))[:7]
-        assert idx[i].tolist() == order.tolist()
-        assert dist[i].tolist() == full[i][order].tolist()
+    for route in ("scan", "block"):
+        idx, dist = oracle.knn(Q, R, 7, route=route)
+        for i in range(Q.shape[0]):
+            order = np.lexsort((np.arange(R.shape[0]), full[i]))[:7]
+            assert idx[i].tolist() == order.tolist()
+            assert dist[i].tolist() == full[i][order].tolist()
+
+
+@pytest.mark.parametrize("n,N", [(1, 1), (3, 15), (4, 16), (65, 17), (130, 47), (64, 200)])
+def test_block_route_ragged(n, N):
+    """The blocked route's query blocks (64), query groups (4) and reference
+    groups (16) end raggedly: every size still gives the scan route's
+    lists, for u8 and for float data, and the per-class minima of the same
+    pass are Algorithm 1's D_C(d) (numpy enumeration)."""
+    rng = np.random.default_rng(n * 1000 + N)
+    R = rng.integers(0, 6, size=(N, 40)).astype(np.uint8)
+    Q = rng.integers(0, 6, size=(n, 40)).astype(np.uint8)
+    labels = rng.integers(0, 3, size=N).astype(np.int32)
+    for kp in sorted({1, min(5, N), N}):
+        i1, d1 = oracle.knn(Q, R, kp, route="scan")
+        i2, d2, D = oracle.knn_class_block(Q, R, labels, 4, kp)      # class 3 is empty
+        assert np.array_equal(i1, i2) and np.array_equal(d1, d2)
+        full = np.sum((Q[:, None, :].astype(np.int64) - R[None, :, :].astype(np.int64)) ** 2, axis=2)
+        for c in range(4):
+            have = labels == c
+            want = full[:, have].min(axis=1) if have.any() else np.full(n, np.iinfo(np.int64).max)
+            assert np.array_equal(D[:, c], want)
+        Rf = rng.standard_normal((N, 40)).astype(np.float32)
+        Qf = rng.standard_normal((n, 40)).astype(np.float32)
+        Rf[N // 2] = Rf[0]                                             # a duplicate row
+        i1, d1 = oracle.knn(Qf, Rf, kp, route="scan")
+        i2, d2 = oracle.knn(Qf, Rf, kp, route="block")
+        assert np.array_equal(i1, i2) and np.array_equal(d1, d2)
 
 
 @pytest.mark.parametrize("seed", range(8))
@@ -232,7 +262,7 @@ def test_float_routes_match_integer_routes_exactly():
     k = 4
     ti, ci, ii, di = oracle.classify(Q, R, labels, 4, off, k)
     Qf, Rf = Q.astype(np.float32) / 8, R.astype(np.float32) / 8
-    for route in ("sort", "scan"):
+    for route in ("sort", "scan", "block"):
         tf, cf, idf, dfl = oracle.classify(Qf, Rf, labels, 4, off, k, route=route)
         assert np.array_equal(idf, ii)
         assert np.array_equal(dfl * 64, di.astype(np.float64))
@@ -251,8 +281,13 @@ def test_float_routes_agree_random():
     i1, d1 = oracle.knn(Q, R, 11, route="sort")
     i2, d2 = oracle.knn(Q, R, 11, route="scan")
     i3, d3 = oracle.knn_expanded(Q, R, 11, chunk=64)
+    i4, d4 = oracle.knn(Q, R, 11, route="block")
     assert np.array_equal(i1, i2) and np.array_equal(d1, d2)
     assert np.array_equal(i1, i3) and np.array_equal(d1, d3)
+    assert np.array_equal(i1, i4) and np.array_equal(d1, d4)
+    # the block route's distance is the direct form summed in dimension order
+    for i in range(3):
+        assert d4[i, 0] == oracle.sqdist_f32(Q[i], R[i4[i, 0]])
 
 
 def test_expanded_route_larger():
@@ -262,10 +297,15 @@ def test_expanded_route_larger():
     R = rng.integers(0, 256, size=(5000, 128)).astype(np.uint8)
     R[4000:4010] = R[10:20]                       # duplicated rows -> ties
     Q = np.concatenate([rng.integers(0, 256, size=(30, 128)).astype(np.uint8), R[10:14]])
+    labels = (np.arange(5000) % 7).astype(np.int32)
     for kp in (1, 11, 33):
         i1, d1 = oracle.knn(Q, R, kp, route="scan")
         i2, d2 = oracle.knn_expanded(Q, R, kp, chunk=777)
+        i3, d3, D = oracle.knn_class_block(Q, R, labels, 7, kp)
         assert np.array_equal(i1, i2) and np.array_equal(d1, d2)
+        assert np.array_equal(i1, i3) and np.array_equal(d1, d3)
+        D2, kth = oracle.class_nn(Q, R, labels, 7, kp - 1)
+        assert np.array_equal(D, D2) and np.array_equal(d3[:, -1], kth)
 
 
 def test_rejects_bad_arguments():
@@ -287,7 +327,7 @@ def test_knn_160_against_full_enumeration():
     Q[2] = R[11]                       # an exact match
     diff = Q[:, None, :].astype(np.int64) - R[None, :, :].astype(np.int64)
     full = np.sum(diff * diff, axis=2)
-    for route in ("scan", "sort", "expanded"):
+    for route in ("scan", "sort", "block", "expanded"):
         if route == "expanded":
             idx, dist = oracle.knn_expanded(Q, R, 12, chunk=13)
         else:
