@@ -148,6 +148,15 @@ int lnbnn_index_info(const lnbnn_index *ix, int64_t *n_refs, int32_t *n_classes,
  * LNBNN_DEVICE_PTRS: queries and outputs are device pointers; the call
  * returns once the work is enqueued on `stream` (outputs valid when the
  * stream reaches that point); img_offsets is still host memory.
+ * Batched calls replay a captured launch sequence; one sequence serves
+ * every batch up to power-of-two buckets of its descriptor and image
+ * counts (the data pointers are read on the device), and at most eight
+ * sequences per index are kept (least recently used first out).
+ * The distance kernel's waits for its LDS stages are bounded
+ * (LNBNN_WAIT_SPINS sleep rounds, default 2^20); a wait that gives up makes
+ * the call's results invalid and is reported as LNBNN_EDEVICE by the call
+ * itself when it blocks (host pointers, or LNBNN_TIMING), else by
+ * lnbnn_sync_status.
  * Errors: EINVAL (NULL required pointer, dtype/mode mismatch, mode not
  * materialised, k out of range, bad offsets, n_images < 0), ENOMEM, EDEVICE.
  */
@@ -157,6 +166,12 @@ int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype,
                    int32_t *out_class, void *out_totals,
                    int32_t *out_nbr_idx, float *out_nbr_dist,
                    void *stream);
+
+/* Wait for every lnbnn_classify call enqueued on this index and report
+ * LNBNN_EDEVICE if a distance-kernel launch since the last report gave up a
+ * bounded stage wait (the results of that call are invalid); LNBNN_OK
+ * otherwise.  For LNBNN_DEVICE_PTRS callers, whose calls do not block. */
+int lnbnn_sync_status(lnbnn_index *ix);
 
 /* Device time of the last LNBNN_TIMING classify on this index: the summed
  * durations of the distance + top-(k+1) kernel launches and of the whole
@@ -216,7 +231,9 @@ const char *lnbnn_variant_name(int32_t v);
  * footprint fits the index's HBM budget, packs them into a batch, and keeps
  * up to two batches in flight on separate streams; requests that arrive while
  * a batch runs join the next one.  Results do not depend on the batch a
- * request lands in (exact integer totals; fixed-point float totals).
+ * request lands in (exact modes: exact integer totals; FP8_RERANK: each
+ * image's FP64 totals are summed by one workgroup in a fixed order:
+ * descriptor, then neighbour rank).
  * Errors: EINVAL (bad pointer, n_desc < 0, k, mode, dtype), ENOMEM (the
  * request alone exceeds the budget), EDEVICE.
  */

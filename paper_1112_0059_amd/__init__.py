@@ -87,6 +87,7 @@ def load():
         "lnbnn_classify": ([P, P, ctypes.c_int, P, i32, i32, ctypes.c_int, u32, P, P, P, P, P],
                            ctypes.c_int),
         "lnbnn_last_timing": ([P, ctypes.POINTER(lnbnn_timing)], ctypes.c_int),
+        "lnbnn_sync_status": ([P], ctypes.c_int),
         "lnbnn_autotune": ([P, P, ctypes.c_int, P, i32, i32, ctypes.c_int, ctypes.c_char_p, P, P],
                            ctypes.c_int),
         "lnbnn_set_variant": ([P, ctypes.c_int, i32, i32], ctypes.c_int),
@@ -253,6 +254,12 @@ def lnbnn_classify(ix: Index, queries, img_offsets, k: int, mode: int, flags: in
                                  n_img, int(k), int(mode), int(flags), _ptr(cls), _ptr(tot),
                                  _ptr(ni), _ptr(nd), _stream(queries, stream)))
     return cls, tot, ni, nd
+
+
+def lnbnn_sync_status(ix: Index):
+    """Wait for the index's classify calls; raises LnbnnError(EDEVICE) if a
+    bounded stage wait gave up since the last report."""
+    _check(load().lnbnn_sync_status(ix.handle))
 
 
 def lnbnn_last_timing(ix: Index) -> dict:

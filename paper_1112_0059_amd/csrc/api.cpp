@@ -72,9 +72,10 @@ int index_fmt(const lnbnn_index *ix, int mode)
 Workspace::~Workspace()
 {
     void *ps[] = {q, offsets, bd, part_d, part_i, totals, totals_f64, cls, nbr_idx, nbr_dist,
-                  q8, qsc, cand, upd_cls, upd_delta};
+                  q8, qsc, cand, upd_cls, upd_delta, status};
     for (void *p : ps)
         if (p) (void)hipFree(p);
+    if (h_status) (void)hipHostFree(h_status);
 }
 
 int64_t Workspace::bytes() const
@@ -91,15 +92,61 @@ int64_t Workspace::bytes() const
 int fp8_candidates(int k) { return 4 * k; }
 int dist_list_len(int mode, int k) { return mode == LNBNN_FP8_RERANK ? 2 * k : k + 1; }
 
-static int grow(void **p, int64_t have, int64_t need, size_t elem)
+// (Re)allocate *p for `need` elements.  A buffer being replaced goes to the
+// index's retired list instead of hipFree, which would synchronise the
+// whole device (and break a graph being captured on another thread); the
+// retired buffers are freed with the index.
+static int grow(lnbnn_index *ix, void **p, int64_t need, size_t elem)
 {
-    if (need <= have && *p) return LNBNN_OK;
     if (*p) {
-        LN_HIP(hipFree(*p));
+        std::lock_guard<std::mutex> lock(ix->retired_mu);
+        ix->retired.push_back(*p);
         *p = nullptr;
     }
     LN_HIP(dmalloc(p, (size_t)std::max<int64_t>(need, 1) * elem));
     return LNBNN_OK;
+}
+
+int64_t cap_bucket(int64_t n, int64_t lo)
+{
+    int64_t b = lo;
+    while (b < n) b *= 2;
+    return b;
+}
+
+int32_t wait_spin_limit()
+{
+    const char *e = getenv("LNBNN_WAIT_SPINS");
+    if (!e || !*e) return 1 << 20;
+    const long v = strtol(e, nullptr, 10);
+    return (int32_t)std::max(0L, std::min(v, (long)(1 << 30)));
+}
+
+int status_begin(Workspace &ws, hipStream_t s)
+{
+    if (ws.status_dirty) {
+        LN_HIP(launch_set_i32(ws.status, 0, s));
+        ws.status_dirty = false;
+    }
+    return LNBNN_OK;
+}
+
+int status_end(Workspace &ws, hipStream_t s)
+{
+    LN_HIP(hipMemcpyAsync(ws.h_status, ws.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    return LNBNN_OK;
+}
+
+int status_check(Workspace &ws, hipStream_t s)
+{
+    const int32_t st = *ws.h_status;
+    if (!(st & kStatusWaitGaveUp)) return LNBNN_OK;
+    // the word accumulates until a failure is reported; clear it now
+    LN_HIP(launch_set_i32(ws.status, 0, s));
+    LN_HIP(hipStreamSynchronize(s));
+    *ws.h_status = 0;
+    return set_err(LNBNN_EDEVICE,
+                   "the distance kernel gave up a bounded wait for an LDS stage (results of the call are invalid)");
 }
 
 void drop_graphs(std::map<std::string, GraphEntry> &graphs)
@@ -135,29 +182,35 @@ int ensure_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int64_t img_cap, in
     const int64_t nc = ix->n_classes;
     img_cap = std::max(img_cap, ws.img_cap);
     if (img_cap > ws.img_cap || !ws.bd) {
-        if ((rc = grow((void **)&ws.offsets, 0, 2 * img_cap + 2, 8))) return rc;
-        if ((rc = grow((void **)&ws.bd, 0, img_cap + 1, sizeof(BatchDesc)))) return rc;
-        if ((rc = grow((void **)&ws.totals, 0, img_cap * nc, 8))) return rc;
-        if ((rc = grow((void **)&ws.cls, 0, img_cap, 4))) return rc;
+        if ((rc = grow(ix, (void **)&ws.offsets, 2 * img_cap + 2, 8))) return rc;
+        if ((rc = grow(ix, (void **)&ws.bd, img_cap + 1, sizeof(BatchDesc)))) return rc;
+        if ((rc = grow(ix, (void **)&ws.totals, img_cap * nc, 8))) return rc;
+        if ((rc = grow(ix, (void **)&ws.cls, img_cap, 4))) return rc;
         if (ws.totals_f64 || need_f64)
-            if ((rc = grow((void **)&ws.totals_f64, 0, img_cap * nc, 8))) return rc;
+            if ((rc = grow(ix, (void **)&ws.totals_f64, img_cap * nc, 8))) return rc;
         ws.img_cap = img_cap;
     }
     if (need_f64 && !ws.totals_f64)
-        if ((rc = grow((void **)&ws.totals_f64, 0, ws.img_cap * nc, 8))) return rc;
+        if ((rc = grow(ix, (void **)&ws.totals_f64, ws.img_cap * nc, 8))) return rc;
     if (part > ws.part_cap) {
-        if ((rc = grow((void **)&ws.part_d, 0, part, 4))) return rc;
-        if ((rc = grow((void **)&ws.part_i, 0, part, 4))) return rc;
+        if ((rc = grow(ix, (void **)&ws.part_d, part, 4))) return rc;
+        if ((rc = grow(ix, (void **)&ws.part_i, part, 4))) return rc;
         ws.part_cap = part;
     }
     if (nbr > ws.nbr_cap) {
-        if ((rc = grow((void **)&ws.nbr_idx, 0, nbr, 4))) return rc;
-        if ((rc = grow((void **)&ws.nbr_dist, 0, nbr, 4))) return rc;
+        if ((rc = grow(ix, (void **)&ws.nbr_idx, nbr, 4))) return rc;
+        if ((rc = grow(ix, (void **)&ws.nbr_dist, nbr, 4))) return rc;
         ws.nbr_cap = nbr;
     }
     if (qbytes > ws.qbytes_cap) {
-        if ((rc = grow(&ws.q, 0, qbytes, 1))) return rc;
+        if ((rc = grow(ix, &ws.q, qbytes, 1))) return rc;
         ws.qbytes_cap = qbytes;
+    }
+    if (!ws.status) {
+        if ((rc = grow(ix, (void **)&ws.status, 1, 4))) return rc;
+        LN_HIP(hipHostMalloc((void **)&ws.h_status, sizeof(int32_t), hipHostMallocDefault));
+        *ws.h_status = 0;
+        ws.status_dirty = true;
     }
     ws.q_cap = std::max(ws.q_cap, q_cap);
     return LNBNN_OK;
@@ -171,17 +224,17 @@ int ensure_fp8_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int n_cand, int
     if ((rc = quiesce_ws(ix, ws))) return rc;
     if (&ws == &ix->ws) drop_graphs(ix);
     if (q_cap > ws.q8_cap || !ws.q8) {
-        if ((rc = grow((void **)&ws.q8, 0, q_cap * (kDim / 16), 16))) return rc;
-        if ((rc = grow((void **)&ws.qsc, 0, q_cap, 4))) return rc;
+        if ((rc = grow(ix, (void **)&ws.q8, q_cap * (kDim / 16), 16))) return rc;
+        if ((rc = grow(ix, (void **)&ws.qsc, q_cap, 4))) return rc;
         ws.q8_cap = q_cap;
     }
     if (cand > ws.cand_cap || !ws.cand) {
-        if ((rc = grow((void **)&ws.cand, 0, cand, 4))) return rc;
+        if ((rc = grow(ix, (void **)&ws.cand, cand, 4))) return rc;
         ws.cand_cap = cand;
     }
     if (upd > ws.upd_cap || !ws.upd_cls) {
-        if ((rc = grow((void **)&ws.upd_cls, 0, upd, 4))) return rc;
-        if ((rc = grow((void **)&ws.upd_delta, 0, upd, 8))) return rc;
+        if ((rc = grow(ix, (void **)&ws.upd_cls, upd, 4))) return rc;
+        if ((rc = grow(ix, (void **)&ws.upd_delta, upd, 8))) return rc;
         ws.upd_cap = upd;
     }
     return LNBNN_OK;
@@ -259,24 +312,24 @@ int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_varia
 
 int64_t part_elems(const Plan &p, int64_t q_cap) { return (int64_t)p.n_slices * 2 * q_cap * p.kpb; }
 
-int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t s, hipEvent_t *ev)
+int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t s, hipEvent_t *kev)
 {
     if (fault_injected("launch")) return set_err(LNBNN_EDEVICE, "injected launch failure");
     const bool fp8 = p.fmt == FMT_FP8;
     // every buffer the launches write must hold what this plan writes
     const Workspace *w = io.ws;
-    if (!w || io.q_cap > w->q_cap || io.img_cap > w->img_cap || part_elems(p, io.q_cap) > w->part_cap)
+    if (!w || io.q_cap > w->q_cap || io.img_cap > w->img_cap || part_elems(p, io.q_cap) > w->part_cap ||
+        !w->status)
         return set_err(LNBNN_EINVAL, "internal: workspace smaller than the plan");
     if (fp8 && (io.q_cap > w->q8_cap || io.q_cap * fp8_candidates(io.k) > w->cand_cap ||
                 io.q_cap * io.k > w->upd_cap))
         return set_err(LNBNN_EINVAL, "internal: FP8 workspace smaller than the plan");
-    if (ev) LN_HIP(hipEventRecord(ev[2], s));
     if (fp8)
-        LN_HIP(launch_fp8_qprep(static_cast<const float *>(io.q), io.bd, io.q_cap, io.q8, io.qsc, s));
+        LN_HIP(launch_fp8_qprep(io.bd, io.q_cap, io.q8, io.qsc, s));
     else
         LN_HIP(launch_fill_u64(io.totals, io.img_cap * ix->n_classes, io.bd, ix->n_classes, s));
     DistArgs a{};
-    a.q = fp8 ? static_cast<const void *>(io.q8) : io.q;
+    a.q = fp8 ? static_cast<const void *>(io.q8) : nullptr;
     a.q_scale = io.qsc;
     a.bd = io.bd;
     a.frag = ix->frag[p.fmt];
@@ -292,14 +345,15 @@ int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t
     a.q_cap = io.q_cap;
     a.part_d = io.part_d;
     a.part_i = io.part_i;
-    if (ev) LN_HIP(hipEventRecord(ev[0], s));
+    a.status = w->status;
+    a.spin_limit = wait_spin_limit();
+    if (kev) LN_HIP(hipEventRecord(kev[0], s));
     LN_HIP(launch_dist_topk(p.variant, p.fmt, p.kpb, a, p.grid, s));
-    if (ev) LN_HIP(hipEventRecord(ev[1], s));
+    if (kev) LN_HIP(hipEventRecord(kev[1], s));
     if (fp8) {
         RerankArgs r{};
         r.bd = io.bd;
         r.offsets = io.offsets;
-        r.qf32 = static_cast<const float *>(io.q);
         r.ref_f32 = ix->ref_f32;
         r.labels = ix->labels;
         r.n_refs = ix->n_refs;
@@ -315,13 +369,9 @@ int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t
         r.upd_cls = io.upd_cls;
         r.upd_delta = io.upd_delta;
         r.totals_f64 = io.totals_f64;
-        r.cls = io.cls;
-        r.nbr_idx = io.nbr_idx;
-        r.nbr_dist = io.nbr_dist;
         LN_HIP(launch_rerank(r, io.q_cap, io.img_cap, s));
     } else {
         FinishArgs f{};
-        f.q = io.q;
         f.q_shift = p.fmt == FMT_I8 || p.fmt == FMT_I8L ? 128 : 0;
         f.dim = ix->dim;
         f.bd = io.bd;
@@ -336,12 +386,9 @@ int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t
         f.part_d = io.part_d;
         f.part_i = io.part_i;
         f.totals = io.totals;
-        f.nbr_idx = io.nbr_idx;
-        f.nbr_dist = io.nbr_dist;
         LN_HIP(launch_finish(f, io.q_cap, s));
-        LN_HIP(launch_argmin(io.totals, io.bd, io.img_cap, ix->n_classes, io.cls, s));
+        LN_HIP(launch_argmin(io.totals, io.bd, io.img_cap, ix->n_classes, s));
     }
-    if (ev) LN_HIP(hipEventRecord(ev[3], s));
     return LNBNN_OK;
 }
 
@@ -371,6 +418,9 @@ static int free_index_buffers(lnbnn_index *ix)
     ix->labels = nullptr;
     ix->ref_f32 = nullptr;
     ix->row_scale = nullptr;
+    std::lock_guard<std::mutex> lock(ix->retired_mu);
+    for (void *p : ix->retired) (void)hipFree(p);
+    ix->retired.clear();
     return LNBNN_OK;
 }
 
@@ -423,6 +473,7 @@ extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, in
     for (auto &e : ix->tev) LN_HIP(hipEventCreate(&e));
     LN_HIP(hipEventCreateWithFlags(&ix->ws_free, hipEventDisableTiming));
     hipStream_t s = stream ? (hipStream_t)stream : ix->own_stream;
+    lnbnn_index *ixp = ix.get();
 
     auto fail = [&](int rc) {
         (void)hipStreamSynchronize(s);
@@ -432,7 +483,7 @@ extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, in
 
     // labels: device copy (and validation when they came as device memory)
     int rc;
-    if ((rc = grow((void **)&ix->labels, 0, n_refs, 4))) return fail(rc);
+    if ((rc = grow(ixp, (void **)&ix->labels, n_refs, 4))) return fail(rc);
     if (dev_in) {
         std::vector<int32_t> hl(n_refs);
         hipError_t e = hipMemcpy(hl.data(), labels, n_refs * 4, hipMemcpyDeviceToHost);
@@ -454,28 +505,30 @@ extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, in
     void *staged = nullptr;
     if (dtype == LNBNN_F32) {
         // the FP32 rows stay resident for the exact re-rank
-        if ((rc = grow((void **)&ix->ref_f32, 0, n_refs * kDim, 4))) return fail(rc);
+        if ((rc = grow(ixp, (void **)&ix->ref_f32, n_refs * kDim, 4))) return fail(rc);
         hipError_t e = hipMemcpyAsync(ix->ref_f32, refs, (size_t)rbytes,
                                       dev_in ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return fail(hip_err(e, "hipMemcpyAsync(refs)"));
         d_refs = ix->ref_f32;
     } else if (!dev_in) {
-        if ((rc = grow(&staged, 0, rbytes, 1))) return fail(rc);
-        hipError_t e = hipMemcpyAsync(staged, refs, (size_t)rbytes, hipMemcpyHostToDevice, s);
+        // stream-ordered staging: freeing it does not synchronise the device
+        hipError_t e = fault_injected("alloc") ? hipErrorOutOfMemory : hipMallocAsync(&staged, (size_t)rbytes, s);
+        if (e != hipSuccess) return fail(hip_err(e, "hipMallocAsync(staging)"));
+        e = hipMemcpyAsync(staged, refs, (size_t)rbytes, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) {
-            (void)hipFree(staged);
+            (void)hipFreeAsync(staged, s);
             return fail(hip_err(e, "hipMemcpyAsync(refs)"));
         }
         d_refs = staged;
     }
     float *seed = nullptr;
     int64_t bytes = n_refs * 4 + (dtype == LNBNN_F32 ? rbytes : 0);
-    rc = grow((void **)&seed, 0, ix->n_pad, 4);
+    rc = grow(ixp, (void **)&seed, ix->n_pad, 4);
     if (!rc) bytes += ix->n_pad * 4;
     bool seeded = false;
     if (dtype == LNBNN_F32) {
-        if (!rc) rc = grow((void **)&ix->row_scale, 0, ix->n_pad, 4);
-        if (!rc) rc = grow((void **)&ix->frag[FMT_FP8], 0, ix->n_pad * kDim, 1);
+        if (!rc) rc = grow(ixp, (void **)&ix->row_scale, ix->n_pad, 4);
+        if (!rc) rc = grow(ixp, (void **)&ix->frag[FMT_FP8], ix->n_pad * kDim, 1);
         if (!rc) {
             bytes += ix->n_pad * (4 + kDim);
             hipError_t e = launch_fp8_index(static_cast<const float *>(d_refs), n_refs, ix->n_pad,
@@ -488,7 +541,7 @@ extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, in
     for (int mode : {LNBNN_EXACT_F16, LNBNN_EXACT_BF16}) {
         if (rc || dtype != LNBNN_U8 || !(mode_mask & LNBNN_MODE_BIT(mode))) continue;
         const int fmt = mode_fmt(mode);
-        if ((rc = grow((void **)&ix->frag[fmt], 0, ix->n_pad * kDim * 2, 1))) break;
+        if ((rc = grow(ixp, (void **)&ix->frag[fmt], ix->n_pad * kDim * 2, 1))) break;
         bytes += ix->n_pad * kDim * 2;
         hipError_t e = launch_pack_u8(static_cast<const uint8_t *>(d_refs), n_refs, ix->n_pad, fmt, ix->frag[fmt],
                                       seeded ? nullptr : seed, s);
@@ -503,10 +556,10 @@ extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, in
         // INT8 mode: its own fragments, seeds and parity masks
         const int f8 = index_fmt(ix.get(), LNBNN_EXACT_I8);
         int32_t *iseed = nullptr;
-        rc = grow((void **)&ix->frag[f8], 0, ix->n_pad * dim, 1);
-        if (!rc) rc = grow((void **)&iseed, 0, ix->n_pad, 4);
+        rc = grow(ixp, (void **)&ix->frag[f8], ix->n_pad * dim, 1);
+        if (!rc) rc = grow(ixp, (void **)&iseed, ix->n_pad, 4);
         if (!rc) ix->seed[f8] = reinterpret_cast<float *>(iseed);
-        if (!rc) rc = grow((void **)&ix->parity, 0, ix->n_pad / kTileRows, 4);
+        if (!rc) rc = grow(ixp, (void **)&ix->parity, ix->n_pad / kTileRows, 4);
         if (!rc) {
             bytes += ix->n_pad * (dim + 4) + ix->n_pad / kTileRows * 4;
             hipError_t e = launch_pack_i8(static_cast<const uint8_t *>(d_refs), n_refs, ix->n_pad, dim, ix->frag[f8],
@@ -514,8 +567,8 @@ extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, in
             if (e != hipSuccess) rc = hip_err(e, "pack i8");
         }
     }
+    if (staged) (void)hipFreeAsync(staged, s);
     hipError_t e = hipStreamSynchronize(s);
-    if (staged) (void)hipFree(staged);
     if (rc) {
         if (seed && !seeded) (void)hipFree(seed);
         return fail(rc);
@@ -567,7 +620,7 @@ extern "C" int lnbnn_index_info(const lnbnn_index *ix, int64_t *n_refs, int32_t 
 // ===========================================================================
 // classify
 // ===========================================================================
-static int validate_classify(const lnbnn_index *ix, const void *queries, int dtype, const int64_t *off,
+int lnbnn::validate_classify(const lnbnn_index *ix, const void *queries, int dtype, const int64_t *off,
                              int32_t n_images, int32_t k, int mode, uint32_t flags, bool has_out_class,
                              const int32_t *nbr_idx, const float *nbr_dist)
 {
@@ -597,21 +650,33 @@ static int validate_classify(const lnbnn_index *ix, const void *queries, int dty
 
 std::string lnbnn::graph_key(const Plan &p, const BatchIO &io)
 {
+    // the plan, the capacities and the workspace buffers; the caller's
+    // queries and outputs travel in the batch descriptor
     std::ostringstream o;
     o << p.variant << '/' << p.fmt << '/' << p.kpb << '/' << p.n_slices << '/' << p.tiles_per_slice << '/' << p.chunk_tiles << '/'
-      << p.grid << '/' << io.q_cap << '/' << io.img_cap << '/' << io.k << '/' << io.mode << '/' << io.q << '/'
-      << io.offsets << '/' << io.bd << '/' << io.cls << '/' << io.totals << '/' << io.totals_f64 << '/'
-      << io.nbr_idx << '/' << io.nbr_dist << '/' << io.part_d << '/' << io.part_i;
+      << p.grid << '/' << io.q_cap << '/' << io.img_cap << '/' << io.k << '/' << io.mode << '/' << io.offsets << '/'
+      << io.bd << '/' << io.totals << '/' << io.totals_f64 << '/' << io.part_d << '/' << io.part_i << '/' << io.q8
+      << '/' << io.cand;
     return o.str();
 }
 
-// Replay (capturing on first use) the launch sequence of a batch.
-int lnbnn::launch_graph(std::map<std::string, GraphEntry> &graphs, lnbnn_index *ix, const Plan &p, const BatchIO &io,
-                 hipStream_t s)
+// Replay (capturing on first use) the launch sequence of a batch.  The
+// caller has made sure that no earlier replay of these graphs is still in
+// flight when an entry is evicted (the workspace's work is ordered on one
+// fence, and eviction waits for it).
+int lnbnn::launch_graph(std::map<std::string, GraphEntry> &graphs, uint64_t &clock, lnbnn_index *ix, const Plan &p,
+                        const BatchIO &io, hipStream_t s)
 {
     const std::string key = graph_key(p, io);
     auto it = graphs.find(key);
     if (it == graphs.end()) {
+        if (graphs.size() >= kMaxGraphs) {
+            auto lru = graphs.begin();
+            for (auto g = graphs.begin(); g != graphs.end(); ++g)
+                if (g->second.last_use < lru->second.last_use) lru = g;
+            if (lru->second.exec) LN_HIP(hipGraphExecDestroy(lru->second.exec));
+            graphs.erase(lru);
+        }
         GraphEntry g;
         LN_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         int rc = enqueue_batch(ix, p, io, s, nullptr);
@@ -627,48 +692,51 @@ int lnbnn::launch_graph(std::map<std::string, GraphEntry> &graphs, lnbnn_index *
         if (e != hipSuccess) return hip_err(e, "hipGraphInstantiate");
         it = graphs.emplace(key, g).first;
     }
+    it->second.last_use = ++clock;
     LN_HIP(hipGraphLaunch(it->second.exec, s));
     return LNBNN_OK;
 }
 
+// The plain per-image form: one launch sequence per image, each planned for
+// that image alone (no graph).  With `kev`, the distance-kernel time of every
+// launch is summed.
 static int classify_per_image(lnbnn_index *ix, const void *dq, const int64_t *off, int32_t n_images,
                               int32_t k, int mode, int32_t *cls, int32_t *nbr_idx, float *nbr_dist, hipStream_t s,
-                              hipEvent_t *ev)
+                              hipEvent_t *kev)
 {
     Workspace &ws = ix->ws;
     const int kp = k + 1;
-    (void)kp;
     const int list_len = dist_list_len(mode, k);
     std::vector<Plan> plans(n_images);
     for (int32_t m = 0; m < n_images; ++m) {
         int rc = make_plan(ix, mode, list_len, std::max<int64_t>(1, off[m + 1] - off[m]), -1, &plans[m]);
         if (rc) return rc;
     }
+    const int64_t rb = row_bytes(ix->dtype, ix->dim);
     std::vector<BatchDesc> bds(n_images);
     std::vector<int64_t> offs(2 * (size_t)n_images);
     for (int32_t m = 0; m < n_images; ++m) {
         bds[m].n_q = off[m + 1] - off[m];
         bds[m].n_img = 1;
+        bds[m].q = static_cast<const uint8_t *>(dq) + off[m] * rb;
+        bds[m].cls = cls + m;
+        bds[m].nbr_idx = nbr_idx ? nbr_idx + off[m] * kp : nullptr;
+        bds[m].nbr_dist = nbr_dist ? nbr_dist + off[m] * kp : nullptr;
         offs[2 * m] = 0;
         offs[2 * m + 1] = bds[m].n_q;
     }
     LN_HIP(hipMemcpyAsync(ws.bd, bds.data(), n_images * sizeof(BatchDesc), hipMemcpyHostToDevice, s));
     LN_HIP(hipMemcpyAsync(ws.offsets, offs.data(), offs.size() * 8, hipMemcpyHostToDevice, s));
-    const int64_t rb = row_bytes(ix->dtype, ix->dim);
     double kms = 0;
     for (int32_t m = 0; m < n_images; ++m) {
         BatchIO io;
-        io.q = static_cast<const uint8_t *>(dq) + off[m] * rb;
         io.offsets = ws.offsets + 2 * m;
         io.bd = ws.bd + m;
         io.q_cap = plans[m].q_cap;
         io.img_cap = 1;
         io.k = k;
         io.mode = mode;
-        io.cls = cls + m;
         io.totals = ws.totals + (int64_t)m * ix->n_classes;
-        io.nbr_idx = nbr_idx ? nbr_idx + off[m] * kp : nullptr;
-        io.nbr_dist = nbr_dist ? nbr_dist + off[m] * kp : nullptr;
         io.ws = &ws;
         io.part_d = ws.part_d;
         io.part_i = ws.part_i;
@@ -678,16 +746,16 @@ static int classify_per_image(lnbnn_index *ix, const void *dq, const int64_t *of
         io.cand = ws.cand;
         io.upd_cls = ws.upd_cls;
         io.upd_delta = ws.upd_delta;
-        int rc = enqueue_batch(ix, plans[m], io, s, ev);
+        int rc = enqueue_batch(ix, plans[m], io, s, kev);
         if (rc) return rc;
-        if (ev) {
-            LN_HIP(hipEventSynchronize(ev[1]));
+        if (kev) {
+            LN_HIP(hipEventSynchronize(kev[1]));
             float ms = 0;
-            LN_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            LN_HIP(hipEventElapsedTime(&ms, kev[0], kev[1]));
             kms += ms;
         }
     }
-    if (ev) {
+    if (kev) {
         ix->last_timing.dist_kernel_ms = kms;
         ix->last_timing.dist_launches = n_images;
     }
@@ -708,6 +776,7 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
     const bool dev = flags & LNBNN_DEVICE_PTRS;
     const bool per_image = flags & LNBNN_PER_IMAGE_LAUNCH;
     const bool timed = flags & LNBNN_TIMING;
+    const bool direct = (flags & LNBNN_NO_GRAPH) || timed;   // events inside a graph cannot be read back
     const int kp = k + 1;
     const bool fp8 = mode == LNBNN_FP8_RERANK;
     const int list_len = dist_list_len(mode, k);   // what the distance kernel keeps
@@ -715,8 +784,11 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
     const int64_t rb = row_bytes(dtype, ix->dim);
     const int64_t nc = ix->n_classes;
 
+    // Capacities: a batched call is planned for power-of-two buckets of its
+    // descriptor and image counts, so one captured graph serves every batch
+    // up to the bucket (the data pointers travel in the batch descriptor).
     Plan plan;
-    int64_t part = 0, q_max = 1;
+    int64_t part = 0, q_max = 1, q_cap = 1, img_cap = n_images;
     if (per_image) {
         for (int32_t m = 0; m < n_images; ++m) {
             Plan pm;
@@ -725,14 +797,17 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
             part = std::max(part, part_elems(pm, pm.q_cap));
             q_max = std::max(q_max, nm);
         }
+        q_cap = std::max<int64_t>(1, n_q);
     } else {
-        if ((rc = make_plan(ix, mode, list_len, std::max<int64_t>(1, n_q), -1, &plan))) return rc;
+        q_cap = cap_bucket(n_q, 1024);
+        img_cap = cap_bucket(n_images, 8);
+        if ((rc = make_plan(ix, mode, list_len, q_cap, -1, &plan))) return rc;
         part = part_elems(plan, plan.q_cap);
         q_max = plan.q_cap;
     }
     const bool want_nbr = out_nbr_idx != nullptr;
-    if ((rc = ensure_ws(ix, ix->ws, std::max<int64_t>(1, n_q), n_images, part,
-                        (want_nbr && !dev) ? n_q * kp : 0, dev ? 0 : n_q * rb, fp8)))
+    if ((rc = ensure_ws(ix, ix->ws, q_cap, img_cap, part, (want_nbr && !dev) ? n_q * kp : 0, dev ? 0 : n_q * rb,
+                        fp8)))
         return rc;
     if (fp8 && (rc = ensure_fp8_ws(ix, ix->ws, q_max, fp8_candidates(k), k))) return rc;
     Workspace &ws = ix->ws;
@@ -761,30 +836,24 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
     int32_t *d_nbr_i = want_nbr ? (dev ? out_nbr_idx : ws.nbr_idx) : nullptr;
     float *d_nbr_d = want_nbr ? (dev ? out_nbr_dist : ws.nbr_dist) : nullptr;
 
-    hipEvent_t *ev = nullptr;
+    hipEvent_t *kev = timed ? ix->tev : nullptr;
+    if (timed) LN_HIP(hipEventRecord(ix->tev[2], s));
+    if ((rc = status_begin(ws, s))) return rc;
     if (per_image) {
-        if (timed) ev = ix->tev;
-        if (timed) LN_HIP(hipEventRecord(ix->tev[2], s));
-        rc = classify_per_image(ix, dq, img_offsets, n_images, k, mode, d_cls, d_nbr_i, d_nbr_d, s,
-                                timed ? ix->tev : nullptr);
+        rc = classify_per_image(ix, dq, img_offsets, n_images, k, mode, d_cls, d_nbr_i, d_nbr_d, s, kev);
         if (rc) return rc;
-        if (timed) LN_HIP(hipEventRecord(ix->tev[3], s));
     } else {
-        BatchDesc hb{n_q, n_images};
+        BatchDesc hb{n_q, n_images, dq, d_cls, d_nbr_i, d_nbr_d};
         LN_HIP(hipMemcpyAsync(ws.bd, &hb, sizeof hb, hipMemcpyHostToDevice, s));
         LN_HIP(hipMemcpyAsync(ws.offsets, img_offsets, (size_t)(n_images + 1) * 8, hipMemcpyHostToDevice, s));
         BatchIO io;
-        io.q = dq;
         io.offsets = ws.offsets;
         io.bd = ws.bd;
         io.q_cap = plan.q_cap;
-        io.img_cap = n_images;
+        io.img_cap = img_cap;
         io.k = k;
         io.mode = mode;
-        io.cls = d_cls;
         io.totals = ws.totals;
-        io.nbr_idx = d_nbr_i;
-        io.nbr_dist = d_nbr_d;
         io.ws = &ws;
         io.part_d = ws.part_d;
         io.part_i = ws.part_i;
@@ -794,15 +863,16 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
         io.cand = ws.cand;
         io.upd_cls = ws.upd_cls;
         io.upd_delta = ws.upd_delta;
-        // timed calls launch directly: events recorded inside a captured
-        // graph cannot be read back with hipEventElapsedTime
-        if ((flags & LNBNN_NO_GRAPH) || timed) {
-            if (timed) ev = ix->tev;
-            if ((rc = enqueue_batch(ix, plan, io, s, ev))) return rc;
+        if (direct) {
+            if ((rc = enqueue_batch(ix, plan, io, s, kev))) return rc;
         } else {
-            if ((rc = launch_graph(ix->graphs, ix, plan, io, s))) return rc;
+            if (ix->graphs.size() >= kMaxGraphs && !ix->graphs.count(graph_key(plan, io)) && ix->ws_used)
+                LN_HIP(hipEventSynchronize(ix->ws_free));   // an eviction: no replay in flight
+            if ((rc = launch_graph(ix->graphs, ix->graph_clock, ix, plan, io, s))) return rc;
         }
     }
+    if ((rc = status_end(ws, s))) return rc;
+    if (timed) LN_HIP(hipEventRecord(ix->tev[3], s));
 
     // outputs
     if (out_totals)
@@ -820,20 +890,33 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
     ix->ws_used = true;
     if (!dev) LN_HIP(hipStreamSynchronize(s));
     if (timed) {
-        LN_HIP(hipEventSynchronize(ev[3]));
+        LN_HIP(hipEventSynchronize(ix->tev[3]));
         float ms = 0;
         if (!per_image) {
-            LN_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            LN_HIP(hipEventElapsedTime(&ms, ix->tev[0], ix->tev[1]));
             ix->last_timing.dist_kernel_ms = ms;
             ix->last_timing.dist_launches = 1;
         }
-        LN_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
+        LN_HIP(hipEventElapsedTime(&ms, ix->tev[2], ix->tev[3]));
         ix->last_timing.total_ms = ms;
         ix->last_timing.slices = per_image ? 0 : plan.n_slices;
         ix->last_timing.tile_variant = per_image ? -1 : plan.variant;
         ix->has_timing = true;
     }
+    // a completed sequence (host pointers, or a timed call) reports a
+    // bounded wait that gave up
+    if (!dev || timed) return status_check(ws, s);
     return LNBNN_OK;
+}
+
+extern "C" int lnbnn_sync_status(lnbnn_index *ix)
+{
+    if (!ix) return set_err(LNBNN_EINVAL, "NULL index");
+    std::lock_guard<std::mutex> lock(ix->mu);
+    LN_HIP(hipSetDevice(ix->device));
+    if (!ix->ws_used || !ix->ws.h_status) return LNBNN_OK;
+    LN_HIP(hipEventSynchronize(ix->ws_free));
+    return status_check(ix->ws, ix->own_stream);
 }
 
 extern "C" int lnbnn_last_timing(const lnbnn_index *ix, lnbnn_timing *out)
@@ -941,10 +1024,10 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
             return LNBNN_OK;
         }
     }
-    const int64_t n_q = img_offsets[n_images];
-    std::vector<int32_t> cls(n_images);
+    hipStream_t ts = stream ? (hipStream_t)stream : ix->own_stream;
     int32_t *d_cls = nullptr;
-    LN_HIP(hipMalloc((void **)&d_cls, std::max<int32_t>(1, n_images) * 4));
+    // stream-ordered: freeing it does not synchronise the device
+    LN_HIP(hipMallocAsync((void **)&d_cls, std::max<int32_t>(1, n_images) * 4, ts));
     // distance-kernel time of one (variant, chunk) setting: mean of two runs
     // after one warm-up run
     auto time_setting = [&](int v, int chunk, double *ms) {
@@ -984,8 +1067,7 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
             }
         }
     }
-    (void)hipFree(d_cls);
-    (void)n_q;
+    (void)hipFreeAsync(d_cls, ts);
     if (rc || best < 0) {
         lnbnn_set_variant(ix, mode, k, -1);
         return rc ? rc : set_err(LNBNN_EINVAL, "no variant can serve mode %d with k = %d", mode, k);

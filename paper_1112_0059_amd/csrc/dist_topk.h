@@ -693,10 +693,17 @@ void k_dist_topk(DistArgs a)
         if ((threadIdx.x & 63) == 0)
             __hip_atomic_fetch_add(&s_cnt[i], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     };
+    // Bounded wait: after spin_limit sleep rounds the wave gives up and
+    // reports it in the status word (lane 0, a vector atomic), which the
+    // host turns into an error for the call, so a miscount can neither hang
+    // the GPU nor pass unnoticed.
     auto cnt_wait = [&](int i, uint32_t target) {
-        // bounded: a wrong count could only give wrong results, never a hang
-        for (int it = 0; it < (1 << 20); ++it) {
-            if (__hip_atomic_load(&s_cnt[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= target) break;
+        int it = 0;
+        while (__hip_atomic_load(&s_cnt[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+            if (++it > a.spin_limit) {
+                if ((threadIdx.x & 63) == 0) atomicOr(a.status, kStatusWaitGaveUp);
+                break;
+            }
             __builtin_amdgcn_s_sleep(1);
         }
         asm volatile("" ::: "memory");
@@ -707,6 +714,7 @@ void k_dist_topk(DistArgs a)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int h = lane >> 5, col = lane & 31;
     const int64_t n_q = a.bd->n_q;
+    const void *q_src = a.q ? a.q : a.bd->q;
     const int64_t n_qb = (n_q + QB - 1) / QB;
     const int64_t n_items = n_qb * a.n_slices;
     const int n_chunks = (a.tiles_per_slice + a.chunk_tiles - 1) / a.chunk_tiles;
@@ -734,7 +742,7 @@ void k_dist_topk(DistArgs a)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 qi[nt] = qb * QB + wave * QW + nt * 32 + col;
-                Op::load_b(a.q, a.q_scale, qi[nt], qi[nt] < n_q, h, bq[nt], sb[nt]);
+                Op::load_b(q_src, a.q_scale, qi[nt], qi[nt] < n_q, h, bq[nt], sb[nt]);
             }
 
             float ld[NT][KP];

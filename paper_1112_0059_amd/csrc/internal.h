@@ -19,11 +19,16 @@ constexpr int kMaxFp8K = 32;             // FP8 mode re-ranks 4k <= 128 candidat
 enum Fmt { FMT_F16 = 0, FMT_BF16 = 1, FMT_FP8 = 2, FMT_I8 = 3, FMT_I8L = 4 };
 constexpr int kNumFmt = 5;
 
-// Batch shape read on the device, so one captured launch sequence serves
-// every batch up to the capacity it was captured for.
+// Batch shape and the batch's data pointers, read on the device, so one
+// captured launch sequence serves every batch (and any caller buffers) up
+// to the capacity it was captured for.
 struct BatchDesc {
     int64_t n_q;        // query descriptors in the batch
     int64_t n_img;      // images in the batch
+    const void *q;      // queries [n_q, dim]: u8 (exact modes) or f32 (FP8 mode)
+    int32_t *cls;       // [n_img] argmin class per image
+    int32_t *nbr_idx;   // [n_q, k+1] neighbour indices, or null
+    float *nbr_dist;    // [n_q, k+1] squared distances, or null
 };
 
 // A distance-kernel variant: queries per wave = 32 * nt, reference tiles
@@ -37,7 +42,7 @@ struct Variant {
 };
 
 struct DistArgs {
-    const void *q;              // queries: u8 [n_q, 128] (exact) / fp8 codes (fp8)
+    const void *q;              // FP8 codes [q_cap, 128] (FP8 mode); null: the u8 queries bd->q
     const int32_t *q_scale;     // fp8: per-query exponent bias (else null)
     const BatchDesc *bd;        // device batch descriptor
     const uint4 *frag;          // packed reference fragments
@@ -51,12 +56,16 @@ struct DistArgs {
     int64_t q_cap;              // capacity: part buffers are laid out for q_cap queries
     float *part_d;              // [n_slices * 2][q_cap][kp]
     int32_t *part_i;
+    int32_t *status;            // bit 0 set by a wave whose bounded stage wait gave up
+    int32_t spin_limit;         // sleep rounds a stage wait allows before it gives up
 };
+
+// Bits of the device status word of a launch sequence.
+constexpr int32_t kStatusWaitGaveUp = 1;
 
 struct RerankArgs {
     const BatchDesc *bd;
     const int64_t *offsets;     // device [n_img + 1]
-    const float *qf32;          // f32 queries [n_q, 128]
     const float *ref_f32;       // f32 references [n_refs, 128]
     const int32_t *labels;
     int64_t n_refs;
@@ -72,14 +81,11 @@ struct RerankArgs {
     int32_t *upd_cls;           // [q_cap, k]: class of the update of rank j, -1 if none
     double *upd_delta;          // [q_cap, k]
     double *totals_f64;         // [n_img, n_classes]
-    int32_t *cls;               // [n_img]
-    int32_t *nbr_idx;           // [n_q, k+1] or null
-    float *nbr_dist;
 };
 
 struct FinishArgs {
-    const void *q;              // u8 queries [n_q, dim] (for ||q - shift||^2)
-    int32_t dim;                // 128, or 160 (location-augmented, INT8 mode)
+    int32_t dim;                // row length of the u8 queries bd->q (for ||q - shift||^2):
+                                // 128, or 160 (location-augmented, INT8 mode)
     int32_t q_shift;            // 0, or 128 where the keys are those of r - 128 and q - 128
     const BatchDesc *bd;
     const int64_t *offsets;     // device [n_img + 1]
@@ -93,8 +99,6 @@ struct FinishArgs {
     const float *part_d;
     const int32_t *part_i;
     unsigned long long *totals; // [n_img, n_classes] int64 (two's complement)
-    int32_t *nbr_idx;           // [n_q, k+1] or null
-    float *nbr_dist;            // [n_q, k+1] or null
 };
 
 // number of kernel variants and their parameters
@@ -144,8 +148,7 @@ hipError_t launch_pack_i8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, in
                           int32_t *seed, uint32_t *parity, hipStream_t s);
 hipError_t launch_fp8_index(const float *refs, int64_t n_refs, int64_t n_pad, uint4 *frag, float *seed,
                             int32_t *row_scale, hipStream_t s);
-hipError_t launch_fp8_qprep(const float *q, const BatchDesc *bd, int64_t q_cap, uint4 *q8, int32_t *qsc,
-                            hipStream_t s);
+hipError_t launch_fp8_qprep(const BatchDesc *bd, int64_t q_cap, uint4 *q8, int32_t *qsc, hipStream_t s);
 hipError_t launch_rerank(const RerankArgs &a, int64_t q_cap, int64_t img_cap, hipStream_t s);
 int grid_for(int64_t n, int block, int cap);
 
@@ -157,6 +160,7 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n_elems_cap, const Bat
                            int32_t n_classes, hipStream_t s);
 hipError_t launch_finish(const FinishArgs &a, int64_t q_cap, hipStream_t s);
 hipError_t launch_argmin(const unsigned long long *totals, const BatchDesc *bd, int64_t img_cap,
-                         int32_t n_classes, int32_t *out_class, hipStream_t s);
+                         int32_t n_classes, hipStream_t s);
+hipError_t launch_set_i32(int32_t *p, int32_t v, hipStream_t s);
 
 }  // namespace lnbnn

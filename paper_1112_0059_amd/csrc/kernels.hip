@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs a)
             ii[p] = bi;
         }
         // ||q - shift||^2 turns the key back into the squared distance
-        const uint4 *qr = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(a.q) + q * a.dim);
+        const uint4 *qr = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(a.bd->q) + q * a.dim);
         uint32_t qq = 0;
         for (int c = 0; c < a.dim / 16; ++c) {
             const uint4 v = qr[c];
@@ -167,10 +167,12 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs a)
                 atomicAdd(a.totals + img * a.n_classes + c, (unsigned long long)delta);
             }
         }
-        if (a.nbr_idx) {
+        int32_t *nbr_idx = a.bd->nbr_idx;
+        float *nbr_dist = a.bd->nbr_dist;
+        if (nbr_idx) {
             for (int p = 0; p < kp; ++p) {
-                a.nbr_idx[q * kp + p] = ii[p];
-                a.nbr_dist[q * kp + p] = dd[p] + (float)qq;
+                nbr_idx[q * kp + p] = ii[p];
+                nbr_dist[q * kp + p] = dd[p] + (float)qq;
             }
         }
     }
@@ -180,9 +182,9 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs a)
 // K3: argmin over classes, lowest class on ties.  One wave per image.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_argmin(const unsigned long long *__restrict__ totals,
-                                                const BatchDesc *bd, int32_t n_classes,
-                                                int32_t *__restrict__ out_class)
+                                                const BatchDesc *bd, int32_t n_classes)
 {
+    int32_t *out_class = bd->cls;
     const int lane = threadIdx.x & 63;
     const int64_t n_img = bd->n_img;
     for (int64_t img = blockIdx.x * 4 + (threadIdx.x >> 6); img < n_img; img += (int64_t)gridDim.x * 4) {
@@ -206,6 +208,11 @@ __global__ __launch_bounds__(256) void k_argmin(const unsigned long long *__rest
         }
         if (lane == 0) out_class[img] = bc;
     }
+}
+
+__global__ void k_set_i32(int32_t *p, int32_t v)
+{
+    if (threadIdx.x == 0) *p = v;
 }
 
 __global__ void k_fill_u64(unsigned long long *p, const BatchDesc *bd, int32_t n_classes, int64_t cap)
@@ -376,9 +383,17 @@ hipError_t launch_finish(const FinishArgs &a, int64_t q_cap, hipStream_t s)
 }
 
 hipError_t launch_argmin(const unsigned long long *totals, const BatchDesc *bd, int64_t img_cap,
-                         int32_t n_classes, int32_t *out_class, hipStream_t s)
+                         int32_t n_classes, hipStream_t s)
 {
-    k_argmin<<<grid_for(img_cap, 4, 16384), 256, 0, s>>>(totals, bd, n_classes, out_class);
+    k_argmin<<<grid_for(img_cap, 4, 16384), 256, 0, s>>>(totals, bd, n_classes);
+    return hipGetLastError();
+}
+
+// A one-word store as a kernel (a fill node, not a memset node, when the
+// sequence is captured in a graph).
+hipError_t launch_set_i32(int32_t *p, int32_t v, hipStream_t s)
+{
+    k_set_i32<<<1, 64, 0, s>>>(p, v);
     return hipGetLastError();
 }
 

@@ -101,10 +101,10 @@ __global__ void k_fp8_pack(const float *__restrict__ refs, int64_t n_refs, int64
 
 // Queries: codes of -q * 2^e_q in natural K order and the E8M0 exponent of
 // 2^(1 - e_q), so the candidate pass accumulates -2 q~.r~.
-__global__ void k_fp8_qprep(const float *__restrict__ q, const BatchDesc *bd, uint4 *__restrict__ q8,
-                            int32_t *__restrict__ qsc)
+__global__ void k_fp8_qprep(const BatchDesc *bd, uint4 *__restrict__ q8, int32_t *__restrict__ qsc)
 {
     const int64_t n_q = bd->n_q;
+    const float *q = static_cast<const float *>(bd->q);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_q; i += (int64_t)gridDim.x * blockDim.x) {
         const float4 *p = reinterpret_cast<const float4 *>(q + i * kDim);
         float m = 0.0f;
@@ -173,6 +173,9 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a)
     const int64_t n_q = a.bd->n_q;
     const int k = a.k;
     const int nc = a.n_cand > 64 ? 2 : 1;       // candidate slots per lane
+    const float *qf32 = static_cast<const float *>(a.bd->q);
+    int32_t *nbr_idx = a.bd->nbr_idx;
+    float *nbr_dist = a.bd->nbr_dist;
     for (int64_t q = blockIdx.x * 4 + (threadIdx.x >> 6); q < n_q; q += (int64_t)gridDim.x * 4) {
         float d[2];
         int idx[2];
@@ -184,7 +187,7 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a)
             if (j >= a.n_cand) continue;
             const int r = a.cand[q * a.n_cand + j];
             if (r < 0 || r >= a.n_refs) continue;
-            const float4 *qr = reinterpret_cast<const float4 *>(a.qf32 + q * kDim);
+            const float4 *qr = reinterpret_cast<const float4 *>(qf32 + q * kDim);
             const float4 *rr = reinterpret_cast<const float4 *>(a.ref_f32 + (int64_t)r * kDim);
             float s = 0.0f;
             for (int t = 0; t < kDim / 4; ++t) {
@@ -236,9 +239,9 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a)
                 a.upd_cls[q * k + rank[c]] = first[c] ? cls[c] : -1;
                 a.upd_delta[q * k + rank[c]] = (double)d[c] - (double)db;
             }
-            if (a.nbr_idx && rank[c] <= k) {
-                a.nbr_idx[q * (k + 1) + rank[c]] = idx[c];
-                a.nbr_dist[q * (k + 1) + rank[c]] = d[c];
+            if (nbr_idx && rank[c] <= k) {
+                nbr_idx[q * (k + 1) + rank[c]] = idx[c];
+                nbr_dist[q * (k + 1) + rank[c]] = d[c];
             }
         }
     }
@@ -297,7 +300,7 @@ __global__ __launch_bounds__(256) void k_img_reduce(RerankArgs a)
             }
             __syncthreads();
         }
-        if (tid == 0) a.cls[img] = s_bc[0] == 0x7fffffff ? 0 : s_bc[0];
+        if (tid == 0) a.bd->cls[img] = s_bc[0] == 0x7fffffff ? 0 : s_bc[0];
         __syncthreads();
     }
 }
@@ -313,10 +316,9 @@ hipError_t launch_fp8_index(const float *refs, int64_t n_refs, int64_t n_pad, ui
     return hipGetLastError();
 }
 
-hipError_t launch_fp8_qprep(const float *q, const BatchDesc *bd, int64_t q_cap, uint4 *q8, int32_t *qsc,
-                            hipStream_t s)
+hipError_t launch_fp8_qprep(const BatchDesc *bd, int64_t q_cap, uint4 *q8, int32_t *qsc, hipStream_t s)
 {
-    k_fp8_qprep<<<grid_for(q_cap, 256, 16384), 256, 0, s>>>(q, bd, q8, qsc);
+    k_fp8_qprep<<<grid_for(q_cap, 256, 16384), 256, 0, s>>>(bd, q8, qsc);
     return hipGetLastError();
 }
 

@@ -55,6 +55,12 @@ struct Workspace {
     int32_t *cand = nullptr;
     int32_t *upd_cls = nullptr;
     double *upd_delta = nullptr;
+    // status word of the launch sequences run on this workspace (bit
+    // kStatusWaitGaveUp: a bounded stage wait gave up), and its pinned host
+    // copy, written after every sequence
+    int32_t *status = nullptr;
+    int32_t *h_status = nullptr;
+    bool status_dirty = false;   // freshly allocated: cleared by the next sequence's stream
     int device = 0;
     ~Workspace();
     int64_t bytes() const;
@@ -98,7 +104,14 @@ struct BatchIO {
 
 struct GraphEntry {
     hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;       // LRU stamp
 };
+
+// Captured launch sequences of one workspace, keyed by plan and capacity
+// bucket (never by the caller's data pointers, which travel in the batch
+// descriptor); at most kMaxGraphs are kept, the least recently used is
+// destroyed first.
+constexpr size_t kMaxGraphs = 8;
 
 struct Server;
 
@@ -130,6 +143,12 @@ struct lnbnn_index {
     std::map<std::pair<int, int>, lnbnn_tuning> pinned;   // (mode, kp bucket) -> launch tuning
     std::map<std::tuple<int, int, int>, int> occupancy;  // (variant, fmt, kpb) -> blocks/CU
     std::map<std::string, lnbnn::GraphEntry> graphs;
+    uint64_t graph_clock = 0;
+    // device buffers replaced by a larger one: kept until the index is
+    // freed, since work in flight (or a graph being captured elsewhere) may
+    // still use them and hipFree would synchronise the whole device
+    std::vector<void *> retired;
+    std::mutex retired_mu;
     lnbnn_timing last_timing{};
     bool has_timing = false;
     hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -142,14 +161,28 @@ struct lnbnn_index {
 
 namespace lnbnn {
 
+// Argument checks shared by the classify entry points (no device call).
+int validate_classify(const lnbnn_index *ix, const void *queries, int dtype, const int64_t *off, int32_t n_images,
+                      int32_t k, int mode, uint32_t flags, bool has_out_class, const int32_t *nbr_idx,
+                      const float *nbr_dist);
 int mode_fmt(int mode);
 int index_fmt(const lnbnn_index *ix, int mode);   // mode_fmt, with the 160-element INT8 tiles where they apply
 int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_variant, Plan *out);
 int64_t part_elems(const Plan &p, int64_t q_cap);
-// Enqueue fill + distance kernel + finish + argmin for one batch.  When
-// `ev` is not null, events 0/1 bracket the distance kernel and 2/3 the whole
-// sequence.
-int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t s, hipEvent_t *ev);
+// Enqueue fill + distance kernel + finish + argmin for one batch (the data
+// pointers come from the batch descriptor io.bd).  When `kev` is not null,
+// events 0/1 bracket the distance kernel.
+int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t s, hipEvent_t *kev);
+// Bounded-wait spin limit for the distance kernel (LNBNN_WAIT_SPINS).
+int32_t wait_spin_limit();
+// Status word handling around a launch sequence on workspace `ws`.
+int status_begin(Workspace &ws, hipStream_t s);
+int status_end(Workspace &ws, hipStream_t s);
+// After the sequence has completed: LNBNN_EDEVICE (and the word cleared) if
+// a bounded wait gave up.
+int status_check(Workspace &ws, hipStream_t s);
+// Capacity bucket: the next power of two >= max(n, lo).
+int64_t cap_bucket(int64_t n, int64_t lo);
 int ensure_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int64_t img_cap, int64_t part,
               int64_t nbr, int64_t qbytes, bool need_f64);
 int ensure_fp8_ws(lnbnn_index *ix, Workspace &ws, int64_t q_cap, int n_cand, int k);
@@ -157,8 +190,8 @@ int fp8_candidates(int k);
 int dist_list_len(int mode, int k);
 int64_t row_bytes(int dtype, int dim);
 
-int launch_graph(std::map<std::string, GraphEntry> &graphs, lnbnn_index *ix, const Plan &p, const BatchIO &io,
-                 hipStream_t s);
+int launch_graph(std::map<std::string, GraphEntry> &graphs, uint64_t &clock, lnbnn_index *ix, const Plan &p,
+                 const BatchIO &io, hipStream_t s);
 void drop_graphs(std::map<std::string, GraphEntry> &graphs);
 std::string graph_key(const Plan &p, const BatchIO &io);
 

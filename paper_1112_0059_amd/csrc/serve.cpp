@@ -64,6 +64,7 @@ struct Slot {
     std::string error;
     bool busy = false;
     std::map<std::string, GraphEntry> graphs;
+    uint64_t graph_clock = 0;
 };
 
 struct Server {
@@ -170,9 +171,8 @@ static int launch_slot(Server *sv, Slot *sl)
         sl->h_off[i + 1] = n_q;
     }
     const int64_t n_img = (int64_t)sl->batch.size();
-    sl->h_bd->n_q = n_q;
-    sl->h_bd->n_img = n_img;
     Workspace &ws = sl->ws;
+    *sl->h_bd = BatchDesc{n_q, n_img, ws.q, ws.cls, nullptr, nullptr};
     LN_HIP(hipMemcpyAsync(ws.q, sl->h_q, (size_t)std::max<int64_t>(rb, n_q * rb), hipMemcpyHostToDevice, sl->stream));
     LN_HIP(hipMemcpyAsync(ws.offsets, sl->h_off, (size_t)(n_img + 1) * 8, hipMemcpyHostToDevice, sl->stream));
     LN_HIP(hipMemcpyAsync(ws.bd, sl->h_bd, sizeof(BatchDesc), hipMemcpyHostToDevice, sl->stream));
@@ -185,14 +185,12 @@ static int launch_slot(Server *sv, Slot *sl)
     int rc = make_plan(ix, mode, dist_list_len(mode, k), std::max<int64_t>(1, bucket), -1, &plan);
     if (rc) return rc;
     BatchIO io;
-    io.q = ws.q;
     io.offsets = ws.offsets;
     io.bd = ws.bd;
     io.q_cap = sv->max_batch_desc;
     io.img_cap = sv->max_images;
     io.k = k;
     io.mode = mode;
-    io.cls = ws.cls;
     io.totals = ws.totals;
     io.totals_f64 = ws.totals_f64;
     io.ws = &ws;
@@ -208,7 +206,11 @@ static int launch_slot(Server *sv, Slot *sl)
     plan.q_cap = sv->max_batch_desc;
     if (part_elems(plan, plan.q_cap) > ws.part_cap)
         return set_err(LNBNN_EINVAL, "launch tuning changed after the serving loop sized its buffers");
-    if ((rc = launch_graph(sl->graphs, ix, plan, io, sl->stream))) return rc;
+    // each batch starts from a clear status word (checked by the completer)
+    LN_HIP(launch_set_i32(ws.status, 0, sl->stream));
+    ws.status_dirty = false;
+    if ((rc = launch_graph(sl->graphs, sl->graph_clock, ix, plan, io, sl->stream))) return rc;
+    if ((rc = status_end(ws, sl->stream))) return rc;
     LN_HIP(hipMemcpyAsync(sl->h_cls, ws.cls, (size_t)n_img * 4, hipMemcpyDeviceToHost, sl->stream));
     LN_HIP(hipMemcpyAsync(sl->h_tot, fp8 ? (const void *)ws.totals_f64 : (const void *)ws.totals,
                           (size_t)(n_img * ix->n_classes * 8), hipMemcpyDeviceToHost, sl->stream));
@@ -288,6 +290,9 @@ static void completer(Server *sv)
             if (e != hipSuccess) {
                 status = LNBNN_EDEVICE;
                 error = std::string("batch failed: ") + hipGetErrorString(e);
+            } else if (*sl->ws.h_status & kStatusWaitGaveUp) {
+                status = LNBNN_EDEVICE;
+                error = "batch failed: the distance kernel gave up a bounded wait for an LDS stage";
             }
         }
         const int64_t t_done = now_ns();
@@ -317,7 +322,8 @@ static int server_start(lnbnn_index *ix)
     if (sv->started) return LNBNN_OK;
     LN_HIP(hipSetDevice(ix->device));
     if (sv->max_images <= 0) sv->max_images = 1024;
-    if (sv->max_batch_desc <= 0) {
+    const bool auto_cap = sv->max_batch_desc <= 0;
+    if (auto_cap) {
         // the largest capacity whose slots fit the budget, at most 2^17
         int64_t cap = 1 << 17;
         while (cap > 1024 && sv->n_slots * slot_bytes(ix, cap, sv->max_images) > ix->hbm_budget) cap /= 2;
@@ -330,7 +336,17 @@ static int server_start(lnbnn_index *ix)
         Slot *sl = new Slot();
         sv->slots.push_back(sl);
         int rc = setup_slot(sv, sl);
-        if (rc) return rc;
+        if (rc) {
+            // undo everything: a later submit starts from scratch
+            const std::string msg = lnbnn_last_error();
+            for (Slot *d : sv->slots) {
+                free_slot(d);
+                delete d;
+            }
+            sv->slots.clear();
+            if (auto_cap) sv->max_batch_desc = 0;
+            return set_err(rc, "%s", msg.c_str());
+        }
     }
     sv->sched = std::thread(scheduler, sv);
     sv->compl_thr = std::thread(completer, sv);
