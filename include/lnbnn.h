@@ -167,6 +167,38 @@ int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype,
                    int32_t *out_nbr_idx, float *out_nbr_dist,
                    void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): the batched
+ * classification of lnbnn_classify with LNBNN_DEVICE_PTRS, which calls no
+ * hipMalloc/hipFree or other allocating routine.  Everything the launch
+ * sequence needs beyond the caller's buffers lives in a library-owned
+ * device array of 64 MiB per GPU, held until the process ends.
+ *
+ *   queries_dev, out_class_dev  device pointers as in lnbnn_classify
+ *   img_offsets  host int64 [n_images + 1] CSR offsets, as in lnbnn_classify
+ *   out_totals_dev  device [n_images, n_classes] totals (int64, or double
+ *               for FP8_RERANK), or NULL
+ *   out_nbr_idx_dev, out_nbr_dist_dev  device [n_desc, k + 1], or NULL
+ *   out_status_dev  device int32 or NULL: set to nonzero if a bounded stage
+ *               wait of the distance kernel gave up (results invalid);
+ *               cleared by the call itself
+ *   stream      hipStream_t (NULL = the index's own); the call returns once
+ *               the work is enqueued (direct launches, no graph)
+ *
+ * Every call on a GPU shares that GPU's scratch array: calls that overlap
+ * on one GPU (other host threads, or streams not ordered after each other)
+ * race on it.  A batch whose scratch need (partial lists, totals when
+ * out_totals_dev is NULL, the FP8 mode's candidate buffers) exceeds the
+ * array is refused with LNBNN_ENOMEM before anything is enqueued.
+ * Errors: as lnbnn_classify, and ENOMEM for a batch too large for the array.
+ */
+int lnbnn_classify_noalloc(lnbnn_index *ix, const void *queries_dev, int dtype,
+                           const int64_t *img_offsets, int32_t n_images, int32_t k, int mode,
+                           int32_t *out_class_dev, void *out_totals_dev,
+                           int32_t *out_nbr_idx_dev, float *out_nbr_dist_dev,
+                           int32_t *out_status_dev, void *stream);
+
 /* Wait for every lnbnn_classify call enqueued on this index and report
  * LNBNN_EDEVICE if a distance-kernel launch since the last report gave up a
  * bounded stage wait (the results of that call are invalid); LNBNN_OK

@@ -88,6 +88,8 @@ def load():
                            ctypes.c_int),
         "lnbnn_last_timing": ([P, ctypes.POINTER(lnbnn_timing)], ctypes.c_int),
         "lnbnn_sync_status": ([P], ctypes.c_int),
+        "lnbnn_classify_noalloc": ([P, P, ctypes.c_int, P, i32, i32, ctypes.c_int, P, P, P, P, P, P],
+                                   ctypes.c_int),
         "lnbnn_autotune": ([P, P, ctypes.c_int, P, i32, i32, ctypes.c_int, ctypes.c_char_p, P, P],
                            ctypes.c_int),
         "lnbnn_set_variant": ([P, ctypes.c_int, i32, i32], ctypes.c_int),
@@ -260,6 +262,20 @@ def lnbnn_sync_status(ix: Index):
     """Wait for the index's classify calls; raises LnbnnError(EDEVICE) if a
     bounded stage wait gave up since the last report."""
     _check(load().lnbnn_sync_status(ix.handle))
+
+
+def lnbnn_classify_noalloc(ix: Index, queries_dev, img_offsets, k: int, mode: int, out: dict,
+                           stream=None):
+    """The allocation-free classify: device tensors only, outputs in `out`
+    (keys "class" required; "totals", "nbr_idx", "nbr_dist", "status"
+    optional), enqueued on torch's current stream (or `stream`)."""
+    offsets = np.ascontiguousarray(img_offsets, dtype=np.int64)
+    _check_width(ix, queries_dev)
+    _check(load().lnbnn_classify_noalloc(
+        ix.handle, _ptr(queries_dev), _dtype_code(queries_dev), _ptr(offsets), offsets.shape[0] - 1,
+        int(k), int(mode), _ptr(out["class"]), _ptr(out.get("totals")), _ptr(out.get("nbr_idx")),
+        _ptr(out.get("nbr_dist")), _ptr(out.get("status")), _stream(queries_dev, stream)))
+    return out
 
 
 def lnbnn_last_timing(ix: Index) -> dict:

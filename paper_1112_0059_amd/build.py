@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblnbnn.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "rerank.hip", "api.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "rerank.hip", "api.cpp", "serve.cpp", "noalloc.hip"]
 INSTANCE_SRC = "dist_inst.hip"
 ARCH = "gfx950"
 FLAGS = [
