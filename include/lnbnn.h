@@ -67,10 +67,22 @@ enum {
     LNBNN_EXACT_F16 = 0,   /* u8 data, FP16 matrix cores, FP32 accumulate: exact */
     LNBNN_EXACT_BF16 = 1,  /* u8 data, BF16 matrix cores, FP32 accumulate: exact */
     LNBNN_FP8_RERANK = 2,  /* f32 data: FP8 e4m3 candidate pass, exact FP32 re-rank of 4k <= 128
-                              candidates (the best 4k FP8 keys of the union of per-row-half
-                              lists of >= 2k keys each; the FP8 top 2k are always among them) */
-    LNBNN_EXACT_I8 = 3     /* u8 data shifted by -128, INT8 matrix cores, INT32 accumulate: exact
+                              candidates.  For k <= 16 the candidates are exactly the 4k
+                              references with the smallest FP8 keys (ties: lower index), for
+                              every launch plan; for k > 16 the best 4k of per-row-half lists
+                              of 64 keys each (the FP8 top 64 are among them) */
+    LNBNN_EXACT_I8 = 3,    /* u8 data shifted by -128, INT8 matrix cores, INT32 accumulate: exact
                               (the fastest exact mode; results identical to FP16/BF16) */
+    LNBNN_FP8_RERANK_2K = 4,  /* as LNBNN_FP8_RERANK with shorter candidate lists: the best 4k FP8
+                              keys of the union of per-row-half lists of 2k keys each (the FP8
+                              top 2k are always among them); faster, and the candidates may
+                              depend on the launch plan.  Built together with FP8_RERANK */
+    LNBNN_NBNN_I8 = 5      /* u8 data: the original NBNN rule (Sec. 1, Algorithm 1; Sec. 3): totals
+                              are sum over the image's descriptors d of ||d - NN_C(d)||^2 for
+                              every class C, the class is their argmin; exact (INT8 matrix
+                              cores on a class-sorted copy of the index, every class padded to
+                              256 rows).  k is not used (Algorithm 1 has none) but must be
+                              valid; no neighbour lists.  Needs every class to own a reference */
 };
 #define LNBNN_MODE_BIT(m) (1u << (m))
 
@@ -93,7 +105,8 @@ enum {
  *              LNBNN_MODE_BIT(LNBNN_EXACT_I8) (queries then carry 160 bytes)
  *   labels     [n_refs] int32 class of every reference, in [0, n_classes)
  *   mode_mask  which search modes to materialise: U8 data allows the exact
- *              modes (F16, BF16, I8), F32 data allows LNBNN_FP8_RERANK
+ *              modes (F16, BF16, I8) and NBNN_I8, F32 data the two FP8 modes
+ *              (they share one packed copy)
  *   hbm_budget_bytes  device workspace cap for the serving loop (0 = 1/4 of
  *              the free device memory after the index is resident)
  *   flags      LNBNN_DEVICE_PTRS: refs and labels are device pointers
@@ -102,7 +115,8 @@ enum {
  *
  * Memory: the packed references stay resident (N x 256 B per FP16/BF16
  * mode, N x dim B for INT8, N x 128 B FP8 plus N x 512 B FP32 for the
- * re-rank), with FP32 norms (4 B) and int32 labels (4 B) per reference.
+ * re-rank, about N x 132 B for the class-sorted NBNN copy), with FP32 norms
+ * (4 B) and int32 labels (4 B) per reference.
  * Errors: EINVAL (NULL pointer, dim not 128 or 160, 160 with other data or
  * modes than u8 INT8, n_refs < 1 or >= 2^31-256,
  * n_classes < 1, label out of range, empty or data-incompatible mode mask),
@@ -138,10 +152,11 @@ int lnbnn_index_info(const lnbnn_index *ix, int64_t *n_refs, int32_t *n_classes,
  *               LNBNN_TIMING
  *   out_class   [n_images] int32 argmin class per image (required)
  *   out_totals  [n_images, n_classes] per-class totals, or NULL: int64 for the
- *               exact modes (exact integers), double for FP8_RERANK
+ *               exact modes and NBNN_I8 (exact integers), double for the FP8
+ *               modes
  *   out_nbr_idx, out_nbr_dist  [n_desc, k + 1] neighbour indices (int32) and
  *               squared distances (float; exact integers in the exact
- *               modes), or NULL
+ *               modes), or NULL (must be NULL for NBNN_I8)
  *   stream      hipStream_t the work is ordered on (NULL = the index's own)
  *
  * Host pointers (default): blocks until outputs are written.

@@ -24,6 +24,8 @@ LNBNN_OK, LNBNN_EINVAL, LNBNN_ENOMEM, LNBNN_EDEVICE = 0, -1, -2, -3
 LNBNN_EAGAIN, LNBNN_ENOENT, LNBNN_EBUSY = -4, -5, -6
 LNBNN_U8, LNBNN_F32 = 0, 1
 LNBNN_EXACT_F16, LNBNN_EXACT_BF16, LNBNN_FP8_RERANK, LNBNN_EXACT_I8 = 0, 1, 2, 3
+LNBNN_FP8_RERANK_2K, LNBNN_NBNN_I8 = 4, 5
+FP8_MODES = (LNBNN_FP8_RERANK, LNBNN_FP8_RERANK_2K)
 LNBNN_DEVICE_PTRS, LNBNN_PER_IMAGE_LAUNCH, LNBNN_NO_GRAPH, LNBNN_TIMING = 1, 2, 4, 8
 LNBNN_DIM = 128
 LNBNN_DIM_LOC = 160
@@ -227,7 +229,7 @@ def lnbnn_classify(ix: Index, queries, img_offsets, k: int, mode: int, flags: in
     n_q = int(offsets[-1]) if n_img >= 0 else 0
     kp = k + 1
     _check_width(ix, queries)
-    float_totals = mode == LNBNN_FP8_RERANK
+    float_totals = mode in FP8_MODES
     dev = _is_torch(queries)
     if dev:
         import torch

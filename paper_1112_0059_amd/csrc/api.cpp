@@ -59,9 +59,13 @@ int mode_fmt(int mode)
     case LNBNN_EXACT_BF16: return FMT_BF16;
     case LNBNN_FP8_RERANK: return FMT_FP8;
     case LNBNN_EXACT_I8: return FMT_I8;
+    case LNBNN_FP8_RERANK_2K: return FMT_FP8;
+    case LNBNN_NBNN_I8: return FMT_I8N;
     }
     return -1;
 }
+
+bool is_fp8_mode(int mode) { return mode == LNBNN_FP8_RERANK || mode == LNBNN_FP8_RERANK_2K; }
 
 int index_fmt(const lnbnn_index *ix, int mode)
 {
@@ -84,13 +88,22 @@ int64_t Workspace::bytes() const
            nbr_cap * 8 + img_cap * 4 + q8_cap * (kDim + 4) + cand_cap * 4 + upd_cap * 12;
 }
 
-// FP8 mode re-ranks 4k candidates per query (at least k + 1).  The
-// distance kernel keeps, per half-lane list, the best 2k FP8 keys (rounded
-// up to a compiled list length); the two halves see disjoint rows, so the
-// union of a query's lists holds at least its 4k best keys' first 2k and
-// the 4k candidates are the best 4k of that union.
+// The FP8 modes re-rank 4k candidates per query (at least k + 1), the best
+// 4k FP8 keys of the union of the distance kernel's lists; lanes l and l+32
+// see disjoint halves of every reference tile and keep separate lists.
+// LNBNN_FP8_RERANK keeps 4k keys per half (up to the 64-entry lists, k <=
+// 16), so the union holds the FP8 top 4k and the candidates are exactly
+// them, whatever the launch plan.  LNBNN_FP8_RERANK_2K keeps 2k per half:
+// faster (shorter lists), and the union still holds the FP8 top 2k.
+// The original NBNN mode keeps one running minimum per class.
 int fp8_candidates(int k) { return 4 * k; }
-int dist_list_len(int mode, int k) { return mode == LNBNN_FP8_RERANK ? 2 * k : k + 1; }
+int dist_list_len(int mode, int k)
+{
+    if (mode == LNBNN_FP8_RERANK) return std::min(4 * k, 64);
+    if (mode == LNBNN_FP8_RERANK_2K) return 2 * k;
+    if (mode == LNBNN_NBNN_I8) return 1;
+    return k + 1;
+}
 
 // (Re)allocate *p for `need` elements.  A buffer being replaced goes to the
 // index's retired list instead of hipFree, which would synchronise the
@@ -257,7 +270,10 @@ static int blocks_per_cu(lnbnn_index *ix, int v, int fmt, int kpb)
 
 static int default_variant(int fmt, int kp)
 {
-    if (fmt == FMT_FP8) return variant_supports(4, fmt, kp) ? 4 : variant_supports(6, fmt, kp) ? 6 : 0;
+    // 8-bit formats: 8-tile stages (8 waves x 64 queries, or 32 queries per
+    // wave where the longer lists need the registers)
+    if (fmt == FMT_FP8 || fmt == FMT_I8 || fmt == FMT_I8N)
+        return variant_supports(8, fmt, kp) ? 8 : variant_supports(11, fmt, kp) ? 11 : 0;
     if (fmt == FMT_I8L) return variant_supports(10, fmt, kp) ? 10 : 11;
     // 8 waves x 64 queries share each LDS stage (half the reference traffic
     // of 4-wave workgroups); 32 queries per wave where the longer neighbour
@@ -284,7 +300,7 @@ int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_varia
     const Variant var = variant(v);
     const int64_t qb = (int64_t)var.waves * 32 * var.nt;
     const int64_t n_qb = std::max<int64_t>(1, (q_cap + qb - 1) / qb);
-    const int64_t n_tiles = ix->n_pad / kTileRows;
+    const int64_t n_tiles = ix->rows[fmt] / kTileRows;
     const int bpc = blocks_per_cu(ix, v, fmt, kpb);
     int64_t resident = (int64_t)ix->cu_count * bpc;
     if (tu.max_workgroups > 0) resident = std::min<int64_t>(resident, tu.max_workgroups);
@@ -312,13 +328,21 @@ int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_varia
 
 int64_t part_elems(const Plan &p, int64_t q_cap) { return (int64_t)p.n_slices * 2 * q_cap * p.kpb; }
 
+int64_t work_elems(const lnbnn_index *ix, const Plan &p, int64_t q_cap)
+{
+    // the original NBNN mode keeps its per-class minima in part_i
+    if (p.fmt == FMT_I8N) return std::max(part_elems(p, q_cap), (int64_t)ix->n_classes * q_cap);
+    return part_elems(p, q_cap);
+}
+
 int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t s, hipEvent_t *kev)
 {
     if (fault_injected("launch")) return set_err(LNBNN_EDEVICE, "injected launch failure");
     const bool fp8 = p.fmt == FMT_FP8;
     // every buffer the launches write must hold what this plan writes
     const Workspace *w = io.ws;
-    if (!w || io.q_cap > w->q_cap || io.img_cap > w->img_cap || part_elems(p, io.q_cap) > w->part_cap ||
+    const bool nbnn = p.fmt == FMT_I8N;
+    if (!w || io.q_cap > w->q_cap || io.img_cap > w->img_cap || work_elems(ix, p, io.q_cap) > w->part_cap ||
         !w->status)
         return set_err(LNBNN_EINVAL, "internal: workspace smaller than the plan");
     if (fp8 && (io.q_cap > w->q8_cap || io.q_cap * fp8_candidates(io.k) > w->cand_cap ||
@@ -326,6 +350,8 @@ int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t
         return set_err(LNBNN_EINVAL, "internal: FP8 workspace smaller than the plan");
     if (fp8)
         LN_HIP(launch_fp8_qprep(io.bd, io.q_cap, io.q8, io.qsc, s));
+    else if (nbnn)
+        LN_HIP(launch_fill_i32(io.part_i, 0x7fffffff, io.q_cap, io.q_cap, ix->n_classes, io.bd, s));
     else
         LN_HIP(launch_fill_u64(io.totals, io.img_cap * ix->n_classes, io.bd, ix->n_classes, s));
     DistArgs a{};
@@ -337,8 +363,9 @@ int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t
     // never read by the unscaled formats; any valid address keeps the
     // kernel's pointer arithmetic defined
     a.row_scale = ix->row_scale ? ix->row_scale : reinterpret_cast<const int32_t *>(a.seed);
-    a.parity = ix->parity ? ix->parity : reinterpret_cast<const uint32_t *>(a.seed);
-    a.n_tiles = ix->n_pad / kTileRows;
+    a.parity = nbnn ? ix->parity_n : ix->parity;
+    if (!a.parity) a.parity = reinterpret_cast<const uint32_t *>(a.seed);
+    a.n_tiles = ix->rows[p.fmt] / kTileRows;
     a.tiles_per_slice = p.tiles_per_slice;
     a.n_slices = p.n_slices;
     a.chunk_tiles = p.chunk_tiles;
@@ -347,6 +374,8 @@ int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t
     a.part_i = io.part_i;
     a.status = w->status;
     a.spin_limit = wait_spin_limit();
+    a.tile_class = nbnn ? ix->tile_class : nullptr;
+    a.cls_min = nbnn ? io.part_i : nullptr;
     if (kev) LN_HIP(hipEventRecord(kev[0], s));
     LN_HIP(launch_dist_topk(p.variant, p.fmt, p.kpb, a, p.grid, s));
     if (kev) LN_HIP(hipEventRecord(kev[1], s));
@@ -370,6 +399,16 @@ int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t
         r.upd_delta = io.upd_delta;
         r.totals_f64 = io.totals_f64;
         LN_HIP(launch_rerank(r, io.q_cap, io.img_cap, s));
+    } else if (nbnn) {
+        NbnnArgs n{};
+        n.bd = io.bd;
+        n.offsets = io.offsets;
+        n.cls_min = io.part_i;
+        n.q_cap = io.q_cap;
+        n.n_classes = ix->n_classes;
+        n.totals = io.totals;
+        LN_HIP(launch_nbnn_totals(n, io.img_cap, s));
+        LN_HIP(launch_argmin(io.totals, io.bd, io.img_cap, ix->n_classes, s));
     } else {
         FinishArgs f{};
         f.q_shift = p.fmt == FMT_I8 || p.fmt == FMT_I8L ? 128 : 0;
@@ -409,9 +448,14 @@ static int free_index_buffers(lnbnn_index *ix)
     if (ix->seed[FMT_FP8]) (void)hipFree(ix->seed[FMT_FP8]);
     if (ix->seed[FMT_I8]) (void)hipFree(ix->seed[FMT_I8]);
     if (ix->seed[FMT_I8L]) (void)hipFree(ix->seed[FMT_I8L]);
+    if (ix->seed[FMT_I8N]) (void)hipFree(ix->seed[FMT_I8N]);
     for (int f = 0; f < kNumFmt; ++f) ix->seed[f] = nullptr;
     if (ix->parity) (void)hipFree(ix->parity);
     ix->parity = nullptr;
+    if (ix->parity_n) (void)hipFree(ix->parity_n);
+    ix->parity_n = nullptr;
+    if (ix->tile_class) (void)hipFree(ix->tile_class);
+    ix->tile_class = nullptr;
     if (ix->labels) (void)hipFree(ix->labels);
     if (ix->ref_f32) (void)hipFree(ix->ref_f32);
     if (ix->row_scale) (void)hipFree(ix->row_scale);
@@ -421,6 +465,56 @@ static int free_index_buffers(lnbnn_index *ix)
     std::lock_guard<std::mutex> lock(ix->retired_mu);
     for (void *p : ix->retired) (void)hipFree(p);
     ix->retired.clear();
+    return LNBNN_OK;
+}
+
+// The class-sorted INT8 copy of the index for the original NBNN rule
+// (Algorithm 1 needs every class's nearest reference): references sorted by
+// class (stable), every class padded to a multiple of 256 rows so that a
+// class never shares a 32-row tile or an 8-tile stage with another, and
+// the class of every tile.  Every class must own a reference.
+struct NbnnHost {
+    std::vector<int32_t> perm, tile_class;
+};
+
+static int build_nbnn_layout(lnbnn_index *ix, const uint8_t *d_refs, const int32_t *hlab, hipStream_t s,
+                             NbnnHost &h, int64_t *bytes)
+{
+    if (ix->dim != kDim) return set_err(LNBNN_EINVAL, "the original NBNN mode takes %d-byte descriptors", kDim);
+    const int32_t nc = ix->n_classes;
+    std::vector<int64_t> cnt(nc, 0), start(nc + 1, 0);
+    for (int64_t j = 0; j < ix->n_refs; ++j) cnt[hlab[j]] += 1;
+    for (int32_t c = 0; c < nc; ++c) {
+        if (cnt[c] == 0)
+            return set_err(LNBNN_EINVAL, "the original NBNN mode needs every class to own a reference (class %d has none)",
+                           c);
+        start[c + 1] = start[c] + (cnt[c] + kPadRows - 1) / kPadRows * kPadRows;
+    }
+    const int64_t n_nb = start[nc];
+    if (n_nb >= (int64_t)0x7fffffff) return set_err(LNBNN_EINVAL, "class-sorted index too large");
+    h.perm.assign(n_nb, -1);
+    std::vector<int64_t> next(start.begin(), start.end() - 1);
+    for (int64_t j = 0; j < ix->n_refs; ++j) h.perm[next[hlab[j]]++] = (int32_t)j;
+    h.tile_class.resize(n_nb / kTileRows);
+    for (int32_t c = 0; c < nc; ++c)
+        for (int64_t t = start[c] / kTileRows; t < start[c + 1] / kTileRows; ++t) h.tile_class[t] = c;
+    int rc;
+    int32_t *d_perm = nullptr, *iseed = nullptr;
+    if ((rc = grow(ix, (void **)&ix->tile_class, n_nb / kTileRows, 4))) return rc;
+    if ((rc = grow(ix, (void **)&ix->frag[FMT_I8N], n_nb * kDim, 1))) return rc;
+    if ((rc = grow(ix, (void **)&iseed, n_nb, 4))) return rc;
+    ix->seed[FMT_I8N] = reinterpret_cast<float *>(iseed);
+    if ((rc = grow(ix, (void **)&ix->parity_n, n_nb / kTileRows, 4))) return rc;
+    *bytes = n_nb * (kDim + 4) + n_nb / kTileRows * 8;
+    LN_HIP(hipMallocAsync((void **)&d_perm, n_nb * 4, s));
+    hipError_t e = hipMemcpyAsync(d_perm, h.perm.data(), n_nb * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ix->tile_class, h.tile_class.data(), h.tile_class.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_pack_i8(d_refs, ix->n_refs, n_nb, kDim, ix->frag[FMT_I8N], iseed, ix->parity_n, s, d_perm);
+    (void)hipFreeAsync(d_perm, s);
+    if (e != hipSuccess) return hip_err(e, "class-sorted pack");
+    ix->rows[FMT_I8N] = n_nb;
     return LNBNN_OK;
 }
 
@@ -441,12 +535,13 @@ extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, in
     if (dtype != LNBNN_U8 && dtype != LNBNN_F32) return set_err(LNBNN_EINVAL, "bad dtype %d", dtype);
     if (hbm_budget_bytes < 0) return set_err(LNBNN_EINVAL, "negative HBM budget");
     const uint32_t exact = LNBNN_MODE_BIT(LNBNN_EXACT_F16) | LNBNN_MODE_BIT(LNBNN_EXACT_BF16) |
-                           LNBNN_MODE_BIT(LNBNN_EXACT_I8);
+                           LNBNN_MODE_BIT(LNBNN_EXACT_I8) | LNBNN_MODE_BIT(LNBNN_NBNN_I8);
+    const uint32_t fp8m = LNBNN_MODE_BIT(LNBNN_FP8_RERANK) | LNBNN_MODE_BIT(LNBNN_FP8_RERANK_2K);
     if (mode_mask == 0) return set_err(LNBNN_EINVAL, "empty mode mask");
     if (dtype == LNBNN_U8 && (mode_mask & ~exact))
         return set_err(LNBNN_EINVAL, "mode mask 0x%x: u8 data builds only the exact modes", mode_mask);
-    if (dtype == LNBNN_F32 && mode_mask != LNBNN_MODE_BIT(LNBNN_FP8_RERANK))
-        return set_err(LNBNN_EINVAL, "mode mask 0x%x: float data builds only the FP8 re-rank mode", mode_mask);
+    if (dtype == LNBNN_F32 && (mode_mask & ~fp8m))
+        return set_err(LNBNN_EINVAL, "mode mask 0x%x: float data builds only the FP8 re-rank modes", mode_mask);
     if (flags & ~(uint32_t)LNBNN_DEVICE_PTRS) return set_err(LNBNN_EINVAL, "unknown flags 0x%x", flags);
     const bool dev_in = flags & LNBNN_DEVICE_PTRS;
     if (!dev_in) {
@@ -484,8 +579,9 @@ extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, in
     // labels: device copy (and validation when they came as device memory)
     int rc;
     if ((rc = grow(ixp, (void **)&ix->labels, n_refs, 4))) return fail(rc);
+    std::vector<int32_t> hl;           // host copy of device labels
     if (dev_in) {
-        std::vector<int32_t> hl(n_refs);
+        hl.resize(n_refs);
         hipError_t e = hipMemcpy(hl.data(), labels, n_refs * 4, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return fail(hip_err(e, "hipMemcpy(labels)"));
         for (int64_t j = 0; j < n_refs; ++j)
@@ -567,6 +663,14 @@ extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, in
             if (e != hipSuccess) rc = hip_err(e, "pack i8");
         }
     }
+    for (int f = 0; f < kNumFmt; ++f) ix->rows[f] = ix->n_pad;
+    NbnnHost nbh;   // host arrays of the class-sorted copy: alive until the sync below
+    if (!rc && (mode_mask & LNBNN_MODE_BIT(LNBNN_NBNN_I8))) {
+        int64_t nb_bytes = 0;
+        rc = build_nbnn_layout(ixp, static_cast<const uint8_t *>(d_refs), dev_in ? hl.data() : labels, s, nbh,
+                               &nb_bytes);
+        bytes += nb_bytes;
+    }
     if (staged) (void)hipFreeAsync(staged, s);
     hipError_t e = hipStreamSynchronize(s);
     if (rc) {
@@ -629,13 +733,15 @@ int lnbnn::validate_classify(const lnbnn_index *ix, const void *queries, int dty
     if (n_images < 0) return set_err(LNBNN_EINVAL, "n_images < 0");
     if (flags & ~(uint32_t)(LNBNN_DEVICE_PTRS | LNBNN_PER_IMAGE_LAUNCH | LNBNN_NO_GRAPH | LNBNN_TIMING))
         return set_err(LNBNN_EINVAL, "unknown flags 0x%x", flags);
-    if (mode < 0 || mode > 3 || !(ix->modes & LNBNN_MODE_BIT(mode)))
+    if (mode < 0 || mode >= kNumModes || !(ix->modes & LNBNN_MODE_BIT(mode)))
         return set_err(LNBNN_EINVAL, "mode %d is not materialised in this index", mode);
-    const int want = mode == LNBNN_FP8_RERANK ? LNBNN_F32 : LNBNN_U8;
+    const int want = is_fp8_mode(mode) ? LNBNN_F32 : LNBNN_U8;
     if (dtype != want) return set_err(LNBNN_EINVAL, "dtype %d does not match mode %d", dtype, mode);
     if (k < 1 || k > LNBNN_MAX_K) return set_err(LNBNN_EINVAL, "k = %d outside [1, %d]", k, LNBNN_MAX_K);
     if ((int64_t)k + 1 > ix->n_refs) return set_err(LNBNN_EINVAL, "k + 1 > n_refs");
-    if (mode == LNBNN_FP8_RERANK) {
+    if (mode == LNBNN_NBNN_I8 && (nbr_idx || nbr_dist))
+        return set_err(LNBNN_EINVAL, "the original NBNN mode returns no neighbour lists");
+    if (is_fp8_mode(mode)) {
         if (k > kMaxFp8K) return set_err(LNBNN_EINVAL, "FP8 re-rank mode needs k <= %d", kMaxFp8K);
         if ((int64_t)fp8_candidates(k) > ix->n_refs) return set_err(LNBNN_EINVAL, "4k > n_refs");
     }
@@ -778,7 +884,7 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
     const bool timed = flags & LNBNN_TIMING;
     const bool direct = (flags & LNBNN_NO_GRAPH) || timed;   // events inside a graph cannot be read back
     const int kp = k + 1;
-    const bool fp8 = mode == LNBNN_FP8_RERANK;
+    const bool fp8 = is_fp8_mode(mode);
     const int list_len = dist_list_len(mode, k);   // what the distance kernel keeps
     const int64_t n_q = img_offsets[n_images];
     const int64_t rb = row_bytes(dtype, ix->dim);
@@ -794,7 +900,7 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
             Plan pm;
             const int64_t nm = std::max<int64_t>(1, img_offsets[m + 1] - img_offsets[m]);
             if ((rc = make_plan(ix, mode, list_len, nm, -1, &pm))) return rc;
-            part = std::max(part, part_elems(pm, pm.q_cap));
+            part = std::max(part, work_elems(ix, pm, pm.q_cap));
             q_max = std::max(q_max, nm);
         }
         q_cap = std::max<int64_t>(1, n_q);
@@ -802,7 +908,7 @@ extern "C" int lnbnn_classify(lnbnn_index *ix, const void *queries, int dtype, c
         q_cap = cap_bucket(n_q, 1024);
         img_cap = cap_bucket(n_images, 8);
         if ((rc = make_plan(ix, mode, list_len, q_cap, -1, &plan))) return rc;
-        part = part_elems(plan, plan.q_cap);
+        part = work_elems(ix, plan, plan.q_cap);
         q_max = plan.q_cap;
     }
     const bool want_nbr = out_nbr_idx != nullptr;
@@ -936,7 +1042,7 @@ extern "C" const char *lnbnn_variant_name(int32_t v) { return variant_name(v); }
 extern "C" int lnbnn_set_tuning(lnbnn_index *ix, int mode, int32_t k, const lnbnn_tuning *t)
 {
     if (!ix || !t) return set_err(LNBNN_EINVAL, "NULL argument");
-    if (mode < 0 || mode > 3 || !(ix->modes & LNBNN_MODE_BIT(mode))) return set_err(LNBNN_EINVAL, "bad mode");
+    if (mode < 0 || mode >= kNumModes || !(ix->modes & LNBNN_MODE_BIT(mode))) return set_err(LNBNN_EINVAL, "bad mode");
     if (k < 1 || k > LNBNN_MAX_K) return set_err(LNBNN_EINVAL, "bad k");
     if (t->chunk_tiles < 0 || t->chunk_tiles % 8 != 0) return set_err(LNBNN_EINVAL, "chunk_tiles must be a multiple of 8");
     if (t->max_workgroups < 0) return set_err(LNBNN_EINVAL, "negative max_workgroups");

@@ -72,6 +72,7 @@ static __device__ __forceinline__ int min16(const i32x16 &a)
 // compares a tile's smallest key with the list's KP-th key.
 struct FloatKeys {
     static constexpr int kRow = kDim;     // elements per descriptor
+    static constexpr bool kNbnn = false;  // per-class minima (original NBNN) instead of k+1 lists
     using acc_t = f32x16;
     using gate_t = float;
     static constexpr bool kParity = false;
@@ -204,9 +205,13 @@ struct OpFP8 : FloatKeys {
 // makes a key (see key()).  S K steps: S = 4 for 128-element rows, S = 5
 // for the 160-element location-augmented rows (|D| < 2^23 there, and every
 // key and distance stays below 2^24, still exact in FP32).
-template <int S, int FMT>
+// NBN: the class-sorted index of the original NBNN rule (Algorithm 1): the
+// kernel keeps each query's running minimum key per class instead of a
+// neighbour list (see k_dist_topk).
+template <int S, int FMT, bool NBN = false>
 struct OpI8T {
     static constexpr int kFmt = FMT;
+    static constexpr bool kNbnn = NBN;
     static constexpr int kSteps = S;
     static constexpr int kRow = 32 * S;      // bytes per descriptor
     static constexpr int kAU = 1;
@@ -263,6 +268,7 @@ struct OpI8T {
 };
 using OpI8 = OpI8T<4, FMT_I8>;
 using OpI8L = OpI8T<5, FMT_I8L>;
+using OpI8N = OpI8T<4, FMT_I8N, true>;
 
 // ---------------------------------------------------------------------------
 // K1: distances + top-(k+1).
@@ -281,6 +287,14 @@ using OpI8L = OpI8T<5, FMT_I8L>;
 // wave beats its current KP-th value does the wave walk the 16 registers and
 // insert.  Rows reach a lane in increasing index order, so "strictly less
 // than" on d' alone realises the (distance, index) order.
+//
+// Original NBNN (Op::kNbnn, Algorithm 1).  The index holds the references
+// sorted by class, every class padded to a multiple of 8 tiles, so a class
+// boundary is always a stage boundary.  The list is one entry long: the
+// query's smallest key in the current class.  When a stage starts a new
+// class (and at the end of an item), the entry is flushed into
+// cls_min[class][query] with an atomic minimum and reset; slices and chunks
+// of one class therefore combine exactly.
 // ---------------------------------------------------------------------------
 template <int KP>
 static __device__ __forceinline__ void list_insert(float v, int idx, float (&ld)[KP], int (&li)[KP],
@@ -681,6 +695,7 @@ void k_dist_topk(DistArgs a)
                               : (MT / 2 < MT - 2 ? MT / 2 : MT - 2);
     constexpr int RSC = Op::kScaled ? MT * kTileRows : 1;
     static_assert(MT % 2 == 0, "tiles are processed in pairs");
+    static_assert(!Op::kNbnn || kPrefetch, "per-class minima are built on the 8-bit tile paths");
     static_assert(NB >= 2 && (PD - 1) * LPS < 64, "prefetch depth");
     __shared__ uint4 s_frag[NB][STAGE_U4];
     __shared__ float4 s_seed[NB][MT * 8];
@@ -752,7 +767,7 @@ void k_dist_topk(DistArgs a)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int64_t base = ((int64_t)(slice * 2 + h) * a.q_cap + qi[nt]) * KP;
-                const bool load = c > 0 && qi[nt] < n_q;
+                const bool load = !Op::kNbnn && c > 0 && qi[nt] < n_q;
 #pragma unroll
                 for (int p = 0; p < KP; ++p) {
                     ld[nt][p] = load ? a.part_d[base + p] : __builtin_inff();
@@ -761,6 +776,26 @@ void k_dist_topk(DistArgs a)
                 thr[nt] = ld[nt][KP - 1];
                 gt[nt] = Op::gate_thr(thr[nt]);
             }
+            // Original NBNN: the class of the entries now in the lists, and
+            // their flush into the per-class minima.
+            int cur_cls = 0;
+            if constexpr (Op::kNbnn) cur_cls = a.tile_class[t0];
+            auto nbnn_flush = [&]() {
+                if constexpr (Op::kNbnn) {
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        if (qi[nt] < n_q && ld[nt][0] < __builtin_inff())
+                            atomicMin(a.cls_min + (int64_t)cur_cls * a.q_cap + qi[nt], (int)ld[nt][0]);
+#pragma unroll
+                        for (int p = 0; p < KP; ++p) {
+                            ld[nt][p] = __builtin_inff();
+                            li[nt][p] = -1;
+                        }
+                        thr[nt] = __builtin_inff();
+                        gt[nt] = Op::gate_thr(thr[nt]);
+                    }
+                }
+            };
             // The queries and lists are in registers before any stage copy
             // is in flight.  (The copies are invisible to the compiler: a
             // wait it placed later for these loads would be a vmcnt(0) that
@@ -814,6 +849,8 @@ void k_dist_topk(DistArgs a)
                 TileRegs<Op> tr[2];           // tile m lives in tr[m % 2]
                 tile_load<Op>(s_frag[0], s_seed[0], s_rsc[0], lane, h, tr[0]);
                 for (int st = 0; st < n_st; ++st) {
+                    int st_cls = 0;
+                    if constexpr (Op::kNbnn) st_cls = a.tile_class[t0 + (int64_t)st * MT];
                     {
                         const int sn = st + PF;
                         const int nb = sn % NB;
@@ -847,6 +884,14 @@ void k_dist_topk(DistArgs a)
                         else
                             pipe_step_regs<Op, KP, NT>(acc1, acc0, bq, sb, tr[1], h, thr, gt, ld, li, row_prev,
                                                        a.parity);
+                        // the step of a stage's first tile gated the previous
+                        // stage's last tile: a new class starts after it
+                        if constexpr (Op::kNbnn && m == 0) {
+                            if (st_cls != cur_cls) {
+                                nbnn_flush();
+                                cur_cls = st_cls;
+                            }
+                        }
                         row_prev = row_t;
                     });
                 }
@@ -858,6 +903,8 @@ void k_dist_topk(DistArgs a)
                 TileRegs<Op> tr[2];           // tile m lives in tr[m % 2]
                 tile_load<Op>(s_frag[0], s_seed[0], s_rsc[0], lane, h, tr[0]);
                 for (int st = 0; st < n_st; ++st) {
+                    int st_cls = 0;
+                    if constexpr (Op::kNbnn) st_cls = a.tile_class[t0 + (int64_t)st * MT];
                     {   // stage st + PD goes into the buffer stage st - 1 used
                         const int sn = st + PD;
                         const int64_t ts = t0 + (int64_t)(sn < n_st ? sn : 0) * MT;
@@ -888,6 +935,12 @@ void k_dist_topk(DistArgs a)
                         else
                             pipe_step_regs<Op, KP, NT>(acc1, acc0, bq, sb, tr[1], h, thr, gt, ld, li, row_prev,
                                                        a.parity);
+                        if constexpr (Op::kNbnn && m == 0) {
+                            if (st_cls != cur_cls) {
+                                nbnn_flush();
+                                cur_cls = st_cls;
+                            }
+                        }
                         row_prev = row_t;
                     });
                     buf = (buf + 1) % NB;
@@ -927,6 +980,10 @@ void k_dist_topk(DistArgs a)
             wait_vmcnt<0>();                    // drain the loads past the end of the chunk
             __syncthreads();
             tiles_select<Op, KP, NT>(acc1, thr, gt, ld, li, row_prev, h, a.parity);
+            if constexpr (Op::kNbnn) {
+                nbnn_flush();
+                continue;
+            }
 
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
@@ -969,6 +1026,9 @@ static void *pick_variant(int v)
         if (v == 0) return kernel_ptr<Op, KP, 1, 2, 4, 4>();
         if constexpr (KP <= 40)
             if (v == 6) return kernel_ptr<Op, KP, 1, 4, 8, 4>();
+        // 8-tile stages for one query tile per wave (the longer lists): 4 KB tiles
+        if constexpr (KP <= 40 && Op::kSteps * Op::kAU == 4)
+            if (v == 11) return kernel_ptr<Op, KP, 1, 8, 8, 3>();
         if constexpr (Op::kFmt == FMT_FP8) {
             if constexpr (KP <= 20) {
                 switch (v) {

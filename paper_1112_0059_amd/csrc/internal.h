@@ -15,9 +15,11 @@ constexpr int kMaxKP = 33;               // k + 1 <= 33
 constexpr int kMaxFp8K = 32;             // FP8 mode re-ranks 4k <= 128 candidates
 
 // Element formats of the packed reference tiles (FMT_I8L: INT8 tiles of
-// 160-element rows, five K steps).
-enum Fmt { FMT_F16 = 0, FMT_BF16 = 1, FMT_FP8 = 2, FMT_I8 = 3, FMT_I8L = 4 };
-constexpr int kNumFmt = 5;
+// 160-element rows, five K steps; FMT_I8N: INT8 tiles of the class-sorted
+// copy of the index that the original NBNN rule sweeps).
+enum Fmt { FMT_F16 = 0, FMT_BF16 = 1, FMT_FP8 = 2, FMT_I8 = 3, FMT_I8L = 4, FMT_I8N = 5 };
+constexpr int kNumFmt = 6;
+constexpr int kNumModes = 6;             // search modes of include/lnbnn.h
 
 // Batch shape and the batch's data pointers, read on the device, so one
 // captured launch sequence serves every batch (and any caller buffers) up
@@ -58,6 +60,19 @@ struct DistArgs {
     int32_t *part_i;
     int32_t *status;            // bit 0 set by a wave whose bounded stage wait gave up
     int32_t spin_limit;         // sleep rounds a stage wait allows before it gives up
+    // original NBNN (FMT_I8N): class of every 32-row tile, and the per-class
+    // minimum key of every query, [n_classes][q_cap] (atomic minima)
+    const int32_t *tile_class;
+    int32_t *cls_min;
+};
+
+struct NbnnArgs {
+    const BatchDesc *bd;
+    const int64_t *offsets;     // device [n_img + 1]
+    const int32_t *cls_min;     // [n_classes][q_cap] minimum key per class and query
+    int64_t q_cap;
+    int32_t n_classes;
+    unsigned long long *totals; // [n_img, n_classes] int64: sum over the image of the per-class distances
 };
 
 // Bits of the device status word of a launch sequence.
@@ -135,6 +150,7 @@ int kp_bucket(int kp, int fmt);         // list length compiled for kp (0 = unsu
     X(i8l, OpI8L, FMT_I8L, 16)    \
     X(i8l, OpI8L, FMT_I8L, 21)    \
     X(i8l, OpI8L, FMT_I8L, 33)    \
+    X(i8n, OpI8N, FMT_I8N, 1)     \
     X(fp8, OpFP8, FMT_FP8, 4)     \
     X(fp8, OpFP8, FMT_FP8, 8)     \
     X(fp8, OpFP8, FMT_FP8, 20)    \
@@ -144,8 +160,10 @@ int kp_bucket(int kp, int fmt);         // list length compiled for kp (0 = unsu
 // Upload-side packing.  refs_u8 / refs_f32 are device pointers.
 hipError_t launch_pack_u8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, int fmt,
                           uint4 *frag, float *seed, hipStream_t s);
+// perm (device, may be null): row r of the packed index holds reference
+// perm[r], or padding where perm[r] < 0 (null: row r holds reference r)
 hipError_t launch_pack_i8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, int dim, uint4 *frag,
-                          int32_t *seed, uint32_t *parity, hipStream_t s);
+                          int32_t *seed, uint32_t *parity, hipStream_t s, const int32_t *perm = nullptr);
 hipError_t launch_fp8_index(const float *refs, int64_t n_refs, int64_t n_pad, uint4 *frag, float *seed,
                             int32_t *row_scale, hipStream_t s);
 hipError_t launch_fp8_qprep(const BatchDesc *bd, int64_t q_cap, uint4 *q8, int32_t *qsc, hipStream_t s);
@@ -162,5 +180,8 @@ hipError_t launch_finish(const FinishArgs &a, int64_t q_cap, hipStream_t s);
 hipError_t launch_argmin(const unsigned long long *totals, const BatchDesc *bd, int64_t img_cap,
                          int32_t n_classes, hipStream_t s);
 hipError_t launch_set_i32(int32_t *p, int32_t v, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, int64_t stride, int64_t rows, const BatchDesc *bd,
+                           hipStream_t s);
+hipError_t launch_nbnn_totals(const NbnnArgs &a, int64_t img_cap, hipStream_t s);
 
 }  // namespace lnbnn

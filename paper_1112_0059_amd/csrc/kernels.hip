@@ -8,6 +8,8 @@
 // plus the variant table and the dispatch to the K1 instances.  (The FP8
 // packing, candidate merge, exact re-rank and per-image reduction live in
 // rerank.hip.)
+#include <algorithm>
+
 #include "dist_topk.h"
 
 namespace lnbnn {
@@ -16,20 +18,27 @@ namespace lnbnn {
 // K0: packing of u8 references ([n_refs, Op::kRow] bytes).  Fragment
 // u = (tile * kSteps + s) * 64 + lane holds the K elements lane `lane`
 // supplies at step s for row 32*tile + (lane & 31) (eight FP16/BF16 values,
-// or sixteen int8 values).
+// or sixteen int8 values).  With `perm`, packed row r holds reference
+// perm[r] (padding where perm[r] < 0): the class-sorted copy of the index.
 // ---------------------------------------------------------------------------
+static __device__ __forceinline__ int64_t source_row(const int32_t *perm, int64_t row, int64_t n_refs)
+{
+    if (perm) return perm[row];
+    return row < n_refs ? row : -1;
+}
+
 template <class Op>
 __global__ void k_pack_u8(const uint8_t *__restrict__ refs, int64_t n_refs, int64_t n_frag,
-                          uint4 *__restrict__ frag)
+                          uint4 *__restrict__ frag, const int32_t *__restrict__ perm)
 {
     for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n_frag;
          u += (int64_t)gridDim.x * blockDim.x) {
         const int lane = (int)(u & 63);
         const int s = (int)((u >> 6) % Op::kSteps);
         const int64_t tile = (u >> 6) / Op::kSteps;
-        const int64_t row = tile * kTileRows + (lane & 31);
-        const bool ok = row < n_refs;
-        frag[u] = Op::pack_frag(refs + (ok ? row : 0) * Op::kRow, ok, s, lane >> 5);
+        const int64_t src = source_row(perm, tile * kTileRows + (lane & 31), n_refs);
+        const bool ok = src >= 0;
+        frag[u] = Op::pack_frag(refs + (ok ? src : 0) * Op::kRow, ok, s, lane >> 5);
     }
 }
 
@@ -37,13 +46,16 @@ __global__ void k_pack_u8(const uint8_t *__restrict__ refs, int64_t n_refs, int6
 // s = r - 128 (stored as the int32 bit pattern), 2^30 on padding rows; and
 // per 32-row tile the mask of the rows' ||s||^2 parities (= parity of sum(r)).
 __global__ void k_seed_i8(const uint8_t *__restrict__ refs, int64_t n_refs, int64_t n_pad, int dim,
-                          int32_t *__restrict__ seed, uint32_t *__restrict__ parity)
+                          int32_t *__restrict__ seed, uint32_t *__restrict__ parity,
+                          const int32_t *__restrict__ perm)
 {
     for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < n_pad;
          row += (int64_t)gridDim.x * blockDim.x) {
         int32_t sq = 0, sum = 0;
-        if (row < n_refs) {
-            const uint4 *p = reinterpret_cast<const uint4 *>(refs + row * dim);
+        const int64_t src = source_row(perm, row, n_refs);
+        const bool real = src >= 0;
+        if (real) {
+            const uint4 *p = reinterpret_cast<const uint4 *>(refs + src * dim);
             for (int c = 0; c < dim / 16; ++c) {
                 const uint4 v = p[c];
                 const uint32_t w[4] = {v.x, v.y, v.z, v.w};
@@ -55,9 +67,9 @@ __global__ void k_seed_i8(const uint8_t *__restrict__ refs, int64_t n_refs, int6
                     }
             }
         }
-        seed[row] = row < n_refs ? (sq >> 1) + sum : OpI8::kPadSeed;
+        seed[row] = real ? (sq >> 1) + sum : OpI8::kPadSeed;
         // one 32-row tile per wave half: bit (row & 31) of its mask
-        const uint64_t bits = __builtin_amdgcn_ballot_w64(row < n_refs && (sq & 1));
+        const uint64_t bits = __builtin_amdgcn_ballot_w64(real && (sq & 1));
         const int lane = threadIdx.x & 63;
         if ((lane & 31) == 0) parity[row >> 5] = (uint32_t)(bits >> (lane & 32));
     }
@@ -215,6 +227,59 @@ __global__ void k_set_i32(int32_t *p, int32_t v)
     if (threadIdx.x == 0) *p = v;
 }
 
+// [rows][stride] array: entries [r][0, bd->n_q) set to v.
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t stride, int64_t rows, const BatchDesc *bd)
+{
+    const int64_t n = bd->n_q;
+    for (int64_t r = blockIdx.y; r < rows; r += gridDim.y)
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+            p[r * stride + i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Original NBNN totals (Algorithm 1): totals[img][C] = sum over the image's
+// descriptors d of ||d - NN_C(d)||^2.  cls_min holds the smallest INT8 key
+// of every (class, query); the squared distance is that key plus
+// ||q - 128||^2.  One workgroup per image: each wave takes every 4th class
+// and sums its keys over the image's queries (lanes over queries, 64-bit
+// sums, exact); the norms are summed once per image.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_nbnn_totals(NbnnArgs a)
+{
+    __shared__ long long s_nrm[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t n_img = a.bd->n_img;
+    const uint8_t *qb = static_cast<const uint8_t *>(a.bd->q);
+    for (int64_t img = blockIdx.x; img < n_img; img += gridDim.x) {
+        const int64_t q0 = a.offsets[img], q1 = a.offsets[img + 1];
+        long long nrm = 0;
+        for (int64_t q = q0 + tid; q < q1; q += 256) {
+            const uint4 *qr = reinterpret_cast<const uint4 *>(qb + q * kDim);
+            for (int c = 0; c < kDim / 16; ++c) {
+                const uint4 v = qr[c];
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+                for (int i = 0; i < 4; ++i)
+                    for (int b = 0; b < 4; ++b) {
+                        const int32_t x = (int32_t)((w[i] >> (8 * b)) & 0xffu) - 128;
+                        nrm += x * x;
+                    }
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off);
+        if (lane == 0) s_nrm[wave] = nrm;
+        __syncthreads();
+        nrm = s_nrm[0] + s_nrm[1] + s_nrm[2] + s_nrm[3];
+        for (int c = wave; c < a.n_classes; c += 4) {
+            const int32_t *m = a.cls_min + (int64_t)c * a.q_cap;
+            long long sum = 0;
+            for (int64_t q = q0 + lane; q < q1; q += 64) sum += m[q];
+            for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+            if (lane == 0) a.totals[img * a.n_classes + c] = (unsigned long long)(sum + nrm);
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void k_fill_u64(unsigned long long *p, const BatchDesc *bd, int32_t n_classes, int64_t cap)
 {
     int64_t n = bd->n_img * (int64_t)n_classes;
@@ -239,7 +304,7 @@ static const Variant kVariants[] = {
     {2, 8, 8, 4},   // 8  (4 KB tiles only: INT8, FP8)
     {2, 4, 8, 8},   // 9  (4 KB tiles only: INT8, FP8)
     {2, 8, 8, 3},   // 10 (160-element INT8 rows only)
-    {1, 8, 8, 3},   // 11 (160-element INT8 rows only)
+    {1, 8, 8, 3},   // 11 (8-bit formats: INT8 rows of 128 or 160, FP8 lists up to 40)
 };
 static const char *kVariantNames[] = {"w4_nt1_mt2_nb4", "w4_nt2_mt2_nb4", "w4_nt2_mt4_nb2", "w4_nt2_mt2_nb2",
                                       "w8_nt2_mt4_nb4", "w8_nt2_mt2_nb8", "w8_nt1_mt4_nb4", "w4_nt2_mt4_nb3",
@@ -252,6 +317,7 @@ const char *variant_name(int v) { return (v >= 0 && v < kNumVariants) ? kVariant
 
 int kp_bucket(int kp, int fmt)
 {
+    if (fmt == FMT_I8N) return kp == 1 ? 1 : 0;   // one running minimum per class
     if (fmt == FMT_F16 || fmt == FMT_BF16 || fmt == FMT_I8 || fmt == FMT_I8L) {
         static const int b[] = {2, 6, 11, 16, 21, 33};
         for (int x : b)
@@ -272,7 +338,9 @@ bool variant_supports(int v, int fmt, int kp)
     // 5 KB tiles (160-element INT8 rows) split evenly over the waves only
     // in these stage shapes
     if (fmt == FMT_I8L) return v == 11 || ((v == 2 || v == 7 || v == 10) && b <= 16);
-    if (v == 10 || v == 11) return false;
+    if (v == 10) return false;
+    // one query tile per wave with 8-tile stages: the 4 KB-tile formats
+    if (v == 11) return fmt == FMT_I8 || fmt == FMT_I8N || (fmt == FMT_FP8 && b <= 40);
     // the deep stage variants need the 4 KB tiles of the 8-bit formats
     if ((v == 8 || v == 9) && (fmt == FMT_F16 || fmt == FMT_BF16)) return false;
     // 64-entry lists take a SIMD's whole register file: one wave per SIMD
@@ -333,10 +401,10 @@ hipError_t launch_pack_u8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, in
     const int64_t n_tiles = n_pad / kTileRows;
     if (fmt == FMT_F16) {
         const int64_t n_frag = n_tiles * OpF16::kSteps * 64;
-        k_pack_u8<OpF16><<<grid_for(n_frag, 256, 65536), 256, 0, s>>>(refs, n_refs, n_frag, frag);
+        k_pack_u8<OpF16><<<grid_for(n_frag, 256, 65536), 256, 0, s>>>(refs, n_refs, n_frag, frag, nullptr);
     } else if (fmt == FMT_BF16) {
         const int64_t n_frag = n_tiles * OpBF16::kSteps * 64;
-        k_pack_u8<OpBF16><<<grid_for(n_frag, 256, 65536), 256, 0, s>>>(refs, n_refs, n_frag, frag);
+        k_pack_u8<OpBF16><<<grid_for(n_frag, 256, 65536), 256, 0, s>>>(refs, n_refs, n_frag, frag, nullptr);
     } else {
         return hipErrorInvalidValue;
     }
@@ -350,14 +418,14 @@ hipError_t launch_pack_u8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, in
 }
 
 hipError_t launch_pack_i8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, int dim, uint4 *frag,
-                          int32_t *seed, uint32_t *parity, hipStream_t s)
+                          int32_t *seed, uint32_t *parity, hipStream_t s, const int32_t *perm)
 {
     if (dim == kDim) {
         const int64_t n_frag = (n_pad / kTileRows) * OpI8::kSteps * 64;
-        k_pack_u8<OpI8><<<grid_for(n_frag, 256, 65536), 256, 0, s>>>(refs, n_refs, n_frag, frag);
+        k_pack_u8<OpI8><<<grid_for(n_frag, 256, 65536), 256, 0, s>>>(refs, n_refs, n_frag, frag, perm);
     } else if (dim == kDimLoc) {
         const int64_t n_frag = (n_pad / kTileRows) * OpI8L::kSteps * 64;
-        k_pack_u8<OpI8L><<<grid_for(n_frag, 256, 65536), 256, 0, s>>>(refs, n_refs, n_frag, frag);
+        k_pack_u8<OpI8L><<<grid_for(n_frag, 256, 65536), 256, 0, s>>>(refs, n_refs, n_frag, frag, perm);
     } else {
         return hipErrorInvalidValue;
     }
@@ -365,7 +433,7 @@ hipError_t launch_pack_i8(const uint8_t *refs, int64_t n_refs, int64_t n_pad, in
     if (e != hipSuccess) return e;
     // whole waves over whole tiles: n_pad is a multiple of 256, as is the
     // grid stride
-    k_seed_i8<<<grid_for(n_pad, 256, 65536), 256, 0, s>>>(refs, n_refs, n_pad, dim, seed, parity);
+    k_seed_i8<<<grid_for(n_pad, 256, 65536), 256, 0, s>>>(refs, n_refs, n_pad, dim, seed, parity, perm);
     return hipGetLastError();
 }
 
@@ -386,6 +454,20 @@ hipError_t launch_argmin(const unsigned long long *totals, const BatchDesc *bd, 
                          int32_t n_classes, hipStream_t s)
 {
     k_argmin<<<grid_for(img_cap, 4, 16384), 256, 0, s>>>(totals, bd, n_classes);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, int64_t stride, int64_t rows, const BatchDesc *bd,
+                           hipStream_t s)
+{
+    dim3 grid(grid_for(n, 256, 1024), (unsigned)std::min<int64_t>(std::max<int64_t>(rows, 1), 1024));
+    k_fill_i32<<<grid, 256, 0, s>>>(p, v, stride, rows, bd);
+    return hipGetLastError();
+}
+
+hipError_t launch_nbnn_totals(const NbnnArgs &a, int64_t img_cap, hipStream_t s)
+{
+    k_nbnn_totals<<<grid_for(img_cap, 1, 16384), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 

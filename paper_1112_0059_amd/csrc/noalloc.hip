@@ -78,13 +78,13 @@ extern "C" int lnbnn_classify_noalloc(lnbnn_index *ix, const void *queries_dev, 
     if ((rc = scratch_base(ix->device, &base))) return rc;
     hipStream_t s = stream ? (hipStream_t)stream : ix->own_stream;
     if (n_images == 0) return LNBNN_OK;
-    const bool fp8 = mode == LNBNN_FP8_RERANK;
+    const bool fp8 = is_fp8_mode(mode);
     const int64_t n_q = img_offsets[n_images];
     const int64_t nc = ix->n_classes;
     const int64_t q_cap = std::max<int64_t>(1, n_q);
     Plan plan;
     if ((rc = make_plan(ix, mode, dist_list_len(mode, k), q_cap, -1, &plan))) return rc;
-    const int64_t part = part_elems(plan, q_cap);
+    const int64_t part = work_elems(ix, plan, q_cap);
     const int n_cand = fp8_candidates(k);
 
     // measure, then carve

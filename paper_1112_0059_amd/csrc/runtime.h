@@ -135,6 +135,11 @@ struct lnbnn_index {
     float *ref_f32 = nullptr;       // FP8 mode: FP32 references for the re-rank
     int32_t *row_scale = nullptr;   // FP8 mode: E8M0 exponent of every padded row
     uint32_t *parity = nullptr;     // INT8 mode: per-tile mask of ||r - 128||^2 parities
+    // original NBNN mode: the class-sorted INT8 copy (every class padded to
+    // 256 rows), its parity masks and the class of each of its tiles
+    uint32_t *parity_n = nullptr;
+    int32_t *tile_class = nullptr;
+    int64_t rows[lnbnn::kNumFmt] = {};   // padded rows of each packed format
     int64_t device_bytes = 0;
 
     std::mutex mu;                                     // classify path (workspace, graphs)
@@ -166,9 +171,13 @@ int validate_classify(const lnbnn_index *ix, const void *queries, int dtype, con
                       int32_t k, int mode, uint32_t flags, bool has_out_class, const int32_t *nbr_idx,
                       const float *nbr_dist);
 int mode_fmt(int mode);
+bool is_fp8_mode(int mode);
 int index_fmt(const lnbnn_index *ix, int mode);   // mode_fmt, with the 160-element INT8 tiles where they apply
 int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_variant, Plan *out);
 int64_t part_elems(const Plan &p, int64_t q_cap);
+// Elements of part_d / part_i a plan needs (the lists, or the original NBNN
+// mode's per-class minima, whichever is larger).
+int64_t work_elems(const lnbnn_index *ix, const Plan &p, int64_t q_cap);
 // Enqueue fill + distance kernel + finish + argmin for one batch (the data
 // pointers come from the batch descriptor io.bd).  When `kev` is not null,
 // events 0/1 bracket the distance kernel.

@@ -89,7 +89,7 @@ struct Server {
 
 static int64_t row_bytes_for_mode(const lnbnn_index *ix, int mode)
 {
-    return row_bytes(mode == LNBNN_FP8_RERANK ? LNBNN_F32 : LNBNN_U8, ix->dim);
+    return row_bytes(is_fp8_mode(mode) ? LNBNN_F32 : LNBNN_U8, ix->dim);
 }
 
 // Device bytes of one slot for `cap` descriptors and `img_cap` images.
@@ -98,10 +98,12 @@ static int64_t slot_bytes(lnbnn_index *ix, int64_t cap, int64_t img_cap)
     const bool fp8 = ix->dtype == LNBNN_F32;
     // worst case over the k a request may ask for: the longest lists
     const int kmax = fp8 ? kMaxFp8K : LNBNN_MAX_K;
-    const int list = kp_bucket(dist_list_len(fp8 ? LNBNN_FP8_RERANK : 0, kmax), fp8 ? FMT_FP8 : FMT_F16);
+    int list = 0;
+    for (int mode = 0; mode < kNumModes; ++mode)
+        if (ix->modes & LNBNN_MODE_BIT(mode)) list = std::max(list, kp_bucket(dist_list_len(mode, kmax), index_fmt(ix, mode)));
     const int64_t slices = 32;   // upper bound of the plan's split
     int64_t b = cap * row_bytes_for_mode(ix, fp8 ? LNBNN_FP8_RERANK : 0);
-    b += slices * 2 * cap * (int64_t)list * 8;
+    b += std::max(slices * 2 * cap * (int64_t)list, (int64_t)ix->n_classes * cap) * 8;
     b += img_cap * (16 + 8 + ix->n_classes * 16 + 4) + 16;
     if (fp8) b += cap * (kDim + 4) + cap * (int64_t)fp8_candidates(kmax) * 4 + cap * kmax * 12;
     return b;
@@ -118,14 +120,14 @@ static int setup_slot(Server *sv, Slot *sl)
     const int kmax = fp8 ? kMaxFp8K : LNBNN_MAX_K;
     // partial lists: the largest layout any (mode, k, batch bucket) plans
     int64_t part = 0;
-    for (int mode = 0; mode < 4; ++mode) {
+    for (int mode = 0; mode < kNumModes; ++mode) {
         if (!(ix->modes & LNBNN_MODE_BIT(mode))) continue;
         for (int k = 1; k <= kmax; ++k) {
             const int len = dist_list_len(mode, k);
             for (int64_t q = 1024; ; q = std::min(cap, q * 2)) {
                 Plan p;
                 if (make_plan(ix, mode, len, std::min(q, cap), -1, &p) == LNBNN_OK)
-                    part = std::max(part, part_elems(p, cap));
+                    part = std::max(part, work_elems(ix, p, cap));
                 if (q >= cap) break;
             }
         }
@@ -160,7 +162,7 @@ static int launch_slot(Server *sv, Slot *sl)
     lnbnn_index *ix = sv->ix;
     const int mode = sl->batch[0]->mode;
     const int k = sl->batch[0]->k;
-    const bool fp8 = mode == LNBNN_FP8_RERANK;
+    const bool fp8 = is_fp8_mode(mode);
     const int64_t rb = row_bytes_for_mode(ix, mode);
     int64_t n_q = 0;
     sl->h_off[0] = 0;
@@ -204,7 +206,7 @@ static int launch_slot(Server *sv, Slot *sl)
     // part buffers are laid out for the slot capacity; the plan for the
     // bucket only chooses the split and the grid
     plan.q_cap = sv->max_batch_desc;
-    if (part_elems(plan, plan.q_cap) > ws.part_cap)
+    if (work_elems(ix, plan, plan.q_cap) > ws.part_cap)
         return set_err(LNBNN_EINVAL, "launch tuning changed after the serving loop sized its buffers");
     // each batch starts from a clear status word (checked by the completer)
     LN_HIP(launch_set_i32(ws.status, 0, sl->stream));
@@ -410,12 +412,12 @@ extern "C" int lnbnn_submit(lnbnn_index *ix, const void *queries, int dtype, int
     if (!ix || !ticket) return set_err(LNBNN_EINVAL, "NULL argument");
     if (n_desc < 0) return set_err(LNBNN_EINVAL, "n_desc < 0");
     if (n_desc > 0 && !queries) return set_err(LNBNN_EINVAL, "NULL queries");
-    if (mode < 0 || mode > 3 || !(ix->modes & LNBNN_MODE_BIT(mode)))
+    if (mode < 0 || mode >= kNumModes || !(ix->modes & LNBNN_MODE_BIT(mode)))
         return set_err(LNBNN_EINVAL, "mode %d is not materialised in this index", mode);
-    const int want = mode == LNBNN_FP8_RERANK ? LNBNN_F32 : LNBNN_U8;
+    const int want = is_fp8_mode(mode) ? LNBNN_F32 : LNBNN_U8;
     if (dtype != want) return set_err(LNBNN_EINVAL, "dtype %d does not match mode %d", dtype, mode);
     if (k < 1 || k > LNBNN_MAX_K || (int64_t)k + 1 > ix->n_refs) return set_err(LNBNN_EINVAL, "bad k = %d", k);
-    if (mode == LNBNN_FP8_RERANK && (k > kMaxFp8K || (int64_t)fp8_candidates(k) > ix->n_refs))
+    if (is_fp8_mode(mode) && (k > kMaxFp8K || (int64_t)fp8_candidates(k) > ix->n_refs))
         return set_err(LNBNN_EINVAL, "FP8 re-rank mode needs k <= %d and 4k <= n_refs", kMaxFp8K);
     std::lock_guard<std::mutex> lock(ix->server_mu);
     if (!ix->server) {

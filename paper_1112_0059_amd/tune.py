@@ -15,7 +15,7 @@ import os
 import sys
 import time
 
-MODES = {"f16": 0, "bf16": 1, "fp8": 2, "i8": 3}
+MODES = {"f16": 0, "bf16": 1, "fp8": 2, "i8": 3, "fp8_2k": 4, "nbnn": 5}
 
 
 def main(argv=None):
@@ -36,9 +36,9 @@ def main(argv=None):
 
     cfg = synth.CONFIGS[args.config]
     mode = MODES[args.mode]
-    if (mode == L.LNBNN_FP8_RERANK) != (cfg.kind == "f32"):
+    if (mode in L.FP8_MODES) != (cfg.kind == "f32"):
         sys.exit(f"config {args.config} holds {cfg.kind} descriptors; mode {args.mode} needs "
-                 f"{'f32' if mode == L.LNBNN_FP8_RERANK else 'u8'}")
+                 f"{'f32' if mode in L.FP8_MODES else 'u8'}")
     if args.loc and mode != L.LNBNN_EXACT_I8:
         sys.exit("--loc needs --mode i8")
     R, labels = synth.gen_index(cfg, loc=args.loc)

@@ -8,7 +8,8 @@ its neighbour lists (indices and squared distances of every descriptor),
 and the full lists of every 8th descriptor.
 
 Mid size (101 classes, 2.27M references): 100 images (every 10th), k = 1,
-5 and 10, in each exact mode.
+5 and 10, in each exact mode; the original NBNN rule's totals and classes
+(Algorithm 1) of the same images.
 """
 import os
 import sys
@@ -59,7 +60,7 @@ def mid():
     R, labels = synth.gen_index(cfg)
     Q, off = synth.gen_query_images(cfg, fx["images"])
     assert np.array_equal(off, fx["offsets"]) and int(fx["n_refs"]) == cfg.n_refs
-    mask = sum(L.LNBNN_MODE_BIT(m) for m in EXACT)
+    mask = sum(L.LNBNN_MODE_BIT(m) for m in EXACT) | L.LNBNN_MODE_BIT(L.LNBNN_NBNN_I8)
     ix = L.lnbnn_build_index(R, labels, cfg.n_classes, mask)
     dq = torch.from_numpy(Q).cuda()
     yield fx, off, ix, dq
@@ -77,3 +78,14 @@ def test_mid_whole_images_against_oracle(mid, mode):
         torch.cuda.synchronize()
         compare_exact(fx, off, k, cls.cpu().numpy(), tot.cpu().numpy(), ni.cpu().numpy(), nd.cpu().numpy(),
                       f"mode {mode} k {k}")
+
+
+@pytest.mark.timeout(600)
+def test_mid_nbnn_whole_images_against_oracle(mid):
+    import torch
+    fx, off, ix, dq = mid
+    _say("original NBNN: 100 whole images")
+    cls, tot, _, _ = L.lnbnn_classify(ix, dq, off, 10, L.LNBNN_NBNN_I8)
+    torch.cuda.synchronize()
+    assert np.array_equal(tot.cpu().numpy(), fx["nbnn_totals"])
+    assert np.array_equal(cls.cpu().numpy(), fx["nbnn_classes"])

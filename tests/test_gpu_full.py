@@ -27,6 +27,10 @@ import oracle
 import paper_1112_0059_amd as L
 import synth
 
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+import oracle_fixtures as F  # noqa: E402
+from test_gpu_fixtures import compare_exact  # noqa: E402
+
 pytestmark = pytest.mark.gpu
 GAMMA = 130 * 2.0 ** -24
 CACHE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
@@ -127,6 +131,27 @@ def test_full_exact_sampled_against_oracle(big):
     assert np.array_equal(tot[m], wt[0]) and cls[m] == wc[0]
 
 
+def _fixture_rows(fx, off):
+    """The fixture's images inside the full batch: (image ids, their CSR
+    offsets in the batch's descriptor order, row index map)."""
+    imgs = fx["images"]
+    rows = np.concatenate([np.arange(off[m], off[m + 1]) for m in imgs])
+    assert np.array_equal(np.diff(fx["offsets"]), np.diff(off)[imgs])
+    return imgs, rows
+
+
+@pytest.mark.timeout(900)
+def test_full_exact_whole_images_against_stored_oracle(big):
+    """The 16 stored whole images (every 32nd) of the benchmarked batch:
+    totals, classes, list digests and sampled lists equal the oracle's."""
+    fx = F.load("L")
+    if fx is None:
+        pytest.skip("oracle_L.npz has not been written")
+    cfg, R, labels, Q, off, ix, (cls, tot, ni, nd) = big
+    imgs, rows = _fixture_rows(fx, off)
+    compare_exact(fx, fx["offsets"], 10, cls[imgs], tot[imgs], ni[rows], nd[rows], "INT8 L k 10")
+
+
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("k", [5, 20])
 def test_full_exact_other_k_sampled(big, k):
@@ -142,15 +167,47 @@ def test_full_exact_other_k_sampled(big, k):
     assert _sorted_lists(ni, nd)
     T = _totals_from_lists(ni, nd, labels, cfg.n_classes, off, k)
     assert np.array_equal(T, tot) and np.array_equal(np.argmin(tot, axis=1), cls)
+    fx = F.load("L")
+    if fx is not None:
+        _say(f"16 stored whole images at k={k}")
+        imgs, rows = _fixture_rows(fx, off)
+        compare_exact(fx, fx["offsets"], k, cls[imgs], tot[imgs], ni[rows], nd[rows], f"INT8 L k {k}")
     imgs = [7, 300]
     sel = np.concatenate([np.arange(off[m], off[m] + 32) for m in imgs])
     wi, wd = oracle.knn_expanded(Q[sel], R, k + 1)
     assert np.array_equal(ni[sel], wi) and np.array_equal(nd[sel].astype(np.int64), wd)
-    m = int(np.argmin(np.diff(off)))
-    s, e = int(off[m]), int(off[m + 1])
-    _say(f"oracle classification of image {m} at k={k}")
-    wt, wc, _, _ = oracle.classify(Q[s:e], R, labels, cfg.n_classes, np.array([0, e - s]), k)
-    assert np.array_equal(tot[m], wt[0]) and cls[m] == wc[0]
+
+
+@pytest.mark.timeout(900)
+def test_full_f16_and_nbnn_whole_images_against_stored_oracle(big):
+    """FP16 at the benchmarked size (all 512 images in one batch, k = 10),
+    and the original NBNN rule on the same batch: the 16 stored whole images
+    equal the oracle's (FP16: totals, classes, list digests, sampled lists;
+    NBNN: Algorithm 1's totals and classes)."""
+    import torch
+    fx = F.load("L")
+    if fx is None:
+        pytest.skip("oracle_L.npz has not been written")
+    cfg, R, labels, Q, off, _, _ = big
+    imgs, rows = _fixture_rows(fx, off)
+    dq = torch.from_numpy(Q).cuda()
+    ix = L.lnbnn_build_index(R, labels, cfg.n_classes,
+                             L.LNBNN_MODE_BIT(L.LNBNN_EXACT_F16) | L.LNBNN_MODE_BIT(L.LNBNN_NBNN_I8))
+    try:
+        _bench_launch(ix, dq, off, 10, L.LNBNN_EXACT_F16)
+        _say("FP16: classifying 512 images")
+        cls, tot, ni, nd = L.lnbnn_classify(ix, dq, off, 10, L.LNBNN_EXACT_F16, want_neighbours=True)
+        torch.cuda.synchronize()
+        cls, tot, ni, nd = cls.cpu().numpy(), tot.cpu().numpy(), ni.cpu().numpy(), nd.cpu().numpy()
+        compare_exact(fx, fx["offsets"], 10, cls[imgs], tot[imgs], ni[rows], nd[rows], "FP16 L k 10")
+        del ni, nd
+        _say("original NBNN: classifying 512 images")
+        cls, tot, _, _ = L.lnbnn_classify(ix, dq, off, 10, L.LNBNN_NBNN_I8)
+        torch.cuda.synchronize()
+        assert np.array_equal(tot.cpu().numpy()[imgs], fx["nbnn_totals"])
+        assert np.array_equal(cls.cpu().numpy()[imgs], fx["nbnn_classes"])
+    finally:
+        ix.free()
 
 
 @pytest.fixture(scope="module")
