@@ -11,12 +11,16 @@ resident in HBM.
 
 Prints one JSON line with the throughput (query descriptors/s), the
 roofline of the dominant kernel (distance + top-(k+1), timed with HIP events
-on its launch stream over the timed steps) and the CPU oracle timed on a
-bounded sample of the same workload; then, in the same line, the FP8
-candidate pass + exact FP32 re-rank on float descriptors of the same shape
-("fp8_rerank") and the serving loop under a Poisson request trace with
-p50/p99 image latency for the batched exact, batched FP8 and plain
-per-image exact forms ("serving").
+on its launch stream over the timed steps), the same batch through the
+default launch path (captured graph replays, host-timed) and the CPU oracle
+timed on a bounded sample of the same workload; then, in the same line, the
+original NBNN rule on the same batch ("nbnn_original"), the FP8 candidate
+pass + exact FP32 re-rank on float descriptors of the same shape with both
+candidate rules and their quality against stored FP64 oracle results
+("fp8_rerank", "fp8_rerank_2k"), the serving loop under a Poisson request
+trace with p50/p99 image latency for the batched exact, batched FP8 and
+plain per-image exact forms ("serving"), the class-count sweep for both
+rules ("class_sweep") and the location-augmented rows.
 """
 from __future__ import annotations
 
@@ -67,27 +71,39 @@ def traffic_per_launch():
     return t.get("bytes_per_launch")
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(R, Q, target_s: float = 15.0):
-    """Time the oracle (C route, OpenMP on every host core) on a bounded
-    sample of query descriptors against the full index."""
+    """Time the oracle (its cache-blocked C route, OpenMP on every host core)
+    on a bounded sample of query descriptors against the full index."""
     import oracle
-    n = 16
+    n = 64 * oracle.num_threads()          # one 64-query block per thread at least
     while True:
         t0 = time.perf_counter()
-        oracle.knn(Q[:n], R, 11, route="scan")
+        oracle.knn(Q[:n], R, 11, route="block")
         dt = time.perf_counter() - t0
         if dt >= target_s / 3 or n >= Q.shape[0]:
             break
         n = min(Q.shape[0], max(n * 2, int(n * target_s / max(dt, 1e-3))))
     return {"value": n / dt, "unit": "query descriptors/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{n} query descriptors of image 0 against all 15.36M references, "
-                      f"k+1 = 11 nearest by brute force (oracle scan route); {dt:.1f} s"}
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"the first {n} query descriptors against all 15.36M references, "
+                      f"k+1 = 11 nearest by brute force (oracle block route, int32 direct form); {dt:.1f} s"}
 
 
 def time_exact(args, L, torch, np, ix, dq, off, n_classes, mode, steps, warmup):
-    """Classify the whole batch `steps` times (after `warmup` untimed runs);
-    returns (wall s per step, mean distance-kernel ms, last timing, classes)."""
+    """Classify the whole batch `steps` times (after `warmup` untimed runs)
+    with direct launches and HIP events around the distance kernel; returns
+    (wall s per step, mean distance-kernel ms, last timing, classes)."""
     n_img = off.shape[0] - 1
     out = {"class": torch.empty(n_img, dtype=torch.int32, device="cuda"),
            "totals": torch.empty((n_img, n_classes), dtype=torch.int64, device="cuda")}
@@ -111,21 +127,37 @@ def time_exact(args, L, torch, np, ix, dq, off, n_classes, mode, steps, warmup):
     return dt, float(np.mean(k1_ms)), L.lnbnn_last_timing(ix), out["class"].cpu().numpy()
 
 
+def time_graph(args, L, torch, ix, dq, off, n_classes, mode, steps, f64=False):
+    """The default launch path (captured graph, replayed), host-timed
+    between synchronisations; wall s per step."""
+    n_img = off.shape[0] - 1
+    out = {"class": torch.empty(n_img, dtype=torch.int32, device="cuda"),
+           "totals": torch.empty((n_img, n_classes), dtype=torch.float64 if f64 else torch.int64, device="cuda")}
+    L.lnbnn_classify(ix, dq, off, args.k, mode, out=out)          # capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        L.lnbnn_classify(ix, dq, off, args.k, mode, out=out)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
 def exact_leg(args, L, torch, np, synth):
     cfg = synth.CONFIGS["L"]
     t0 = time.perf_counter()
     R, labels = synth.gen_index(cfg)
     Q, off, true_cls = synth.gen_queries(cfg)
     log(f"generated {R.shape[0]} refs, {Q.shape[0]} queries in {time.perf_counter() - t0:.1f}s")
-    I8, F16 = L.LNBNN_EXACT_I8, L.LNBNN_EXACT_F16
-    ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(I8) | L.LNBNN_MODE_BIT(F16))
+    I8, F16, NB = L.LNBNN_EXACT_I8, L.LNBNN_EXACT_F16, L.LNBNN_NBNN_I8
+    ix = L.lnbnn_build_index(R, labels, cfg.n_classes,
+                             L.LNBNN_MODE_BIT(I8) | L.LNBNN_MODE_BIT(F16) | L.LNBNN_MODE_BIT(NB))
     dq = torch.from_numpy(Q).cuda()
     n_img = off.shape[0] - 1
     tuned = {}
     if os.path.exists(TUNING_CACHE):
         # project autotuner: the cache holds the variant chosen on this
         # workload; a hit pins it without timing anything
-        for mode in (I8, F16):
+        for mode in (I8, F16, NB):
             tuned[mode] = L.lnbnn_autotune(ix, dq, off, args.k, mode, cache_path=TUNING_CACHE)
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -167,6 +199,23 @@ def exact_leg(args, L, torch, np, synth):
                      "kernel_ms": k1_ms, "algorithmic_ops_per_launch": flop},
         "accuracy_statistic": float(np.mean(cls == true_cls)),
     }
+    # the product's default path: the same batch replayed from a captured graph
+    gsteps = max(1, min(args.steps, 5))
+    dtg = time_graph(args, L, torch, ix, dq, off, cfg.n_classes, I8, gsteps)
+    res["graph_path"] = {"ms_per_step": dtg * 1e3, "steps": gsteps, "value": n_q / dtg,
+                         "vs_direct_launches": dt / dtg}
+    log(f"graph path: {dtg * 1e3:.1f} ms per step (direct launches {dt * 1e3:.1f} ms)")
+    # the original NBNN rule (Algorithm 1) on the same batch and index shape
+    nsteps = max(1, min(args.steps, 3))
+    dtn, k1n, tn, clsn = time_exact(args, L, torch, np, ix, dq, off, cfg.n_classes, NB, nsteps, 1)
+    an = flop / (k1n / 1e3) / 1e12
+    res["nbnn_original"] = {"value": n_q / dtn, "unit": "query descriptors/s", "steps": nsteps,
+                            "ms_per_step": dtn * 1e3, "dtype": "i8",
+                            "variant": L.lnbnn_variant_name(tn["tile_variant"]),
+                            "same_classes_as_local": bool(np.array_equal(clsn, cls)),
+                            "accuracy_statistic": float(np.mean(clsn == true_cls)),
+                            "roofline": {"bound": "mfma", "achieved": an, "peak": PEAK_MFMA_I8_TOPS,
+                                         "unit": "TOP/s", "frac": an / PEAK_MFMA_I8_TOPS, "kernel_ms": k1n}}
     if not args.no_f16:
         # the same exact classification on the FP16 matrix cores, for context
         steps16 = max(1, min(args.steps, 2))
@@ -219,58 +268,97 @@ def loc_leg(args, L, torch, np, synth):
             "accuracy_statistic": float(np.mean(cls == true_cls))}
 
 
+def fp8_quality(L, torch, np, ix, dq, off, k, mode, n_classes):
+    """Neighbour recall, identical lists, decision agreement and score error
+    of the FP8 path against stored FP64 oracle results for 64 whole images
+    of this batch (tests/golden/oracle_P.npz, written from the oracle), or
+    None if they have not been written."""
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    try:
+        import oracle_fixtures as F
+        fx = F.load("P")
+    except Exception:
+        return None
+    if fx is None or k != 10:
+        return None
+    imgs = fx["images"]
+    rows = np.concatenate([np.arange(off[m], off[m + 1]) for m in imgs])
+    if not np.array_equal(np.diff(fx["offsets"]), np.diff(off)[imgs]):
+        return {"error": "stored images do not match this batch"}
+    cls, tot, ni, nd = L.lnbnn_classify(ix, dq, off, k, mode, want_neighbours=True)
+    torch.cuda.synchronize()
+    cls, tot, ni = cls.cpu().numpy()[imgs], tot.cpu().numpy()[imgs], ni.cpu().numpy()[rows]
+    wi = fx["nbr_idx"]
+    hits = (ni[:, :, None] == wi[:, None, :]).any(axis=2).sum(axis=1)
+    wt, wc = fx["totals_k10"], fx["classes_k10"]
+    err = np.abs(tot - wt).max(axis=1) / np.abs(wt).max(axis=1)
+    return {"images": int(len(imgs)), "descriptors": int(rows.size),
+            "recall": float(hits.mean() / (k + 1)),
+            "identical_lists": float(np.mean(np.all(ni == wi, axis=1))),
+            "decision_agreement": f"{int(np.sum(cls == wc))}/{len(imgs)}",
+            "max_score_error_rel": float(err.max()),
+            "against": "FP64 oracle (Algorithm 2 on exact kNN), every 8th image of the batch"}
+
+
 def fp8_leg(args, L, torch, np, synth):
     """FP8 candidate pass (4k) + exact FP32 re-rank on float descriptors with
-    config L's structure (its recall against the FP64 oracle is a GPU test)."""
+    config L's structure, with both candidate rules: the FP8 top 4k
+    (LNBNN_FP8_RERANK) and the best 4k of per-row-half lists of 2k
+    (LNBNN_FP8_RERANK_2K); each with its quality against stored FP64 oracle
+    results when they exist."""
     cfg = synth.CONFIGS["P"]
     t0 = time.perf_counter()
     R, labels = synth.gen_index(cfg)
     Q, off, true_cls = synth.gen_queries(cfg)
     log(f"fp8: generated {R.shape[0]} float refs, {Q.shape[0]} queries in {time.perf_counter() - t0:.1f}s")
-    ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(L.LNBNN_FP8_RERANK))
+    FP8, FP8_2K = L.LNBNN_FP8_RERANK, L.LNBNN_FP8_RERANK_2K
+    ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(FP8) | L.LNBNN_MODE_BIT(FP8_2K))
+    del R
     dq = torch.from_numpy(Q).cuda()
     n_img = off.shape[0] - 1
+    n_q = int(Q.shape[0])
+    flop = 2.0 * 128 * cfg.n_refs * n_q
     out = {"class": torch.empty(n_img, dtype=torch.int32, device="cuda"),
            "totals": torch.empty((n_img, cfg.n_classes), dtype=torch.float64, device="cuda")}
-    mode = L.LNBNN_FP8_RERANK
     tuned = os.path.exists(TUNING_CACHE)
-    if tuned:
-        # the tuned launch for this workload (a cache hit times nothing)
-        L.lnbnn_autotune(ix, dq, off, args.k, mode, cache_path=TUNING_CACHE)
-    L.lnbnn_classify(ix, dq, off, args.k, mode, flags=L.LNBNN_TIMING, out=out)
-    torch.cuda.synchronize()
-    steps = max(1, min(args.steps, 3))
-    t0 = time.perf_counter()
-    k1_ms, tot_ms = [], []
-    for i in range(steps):
+    legs = {}
+    for mode, name in ((FP8, "top 4k"), (FP8_2K, "best 4k of per-half 2k lists")):
+        if tuned:
+            # the tuned launch for this workload (a cache hit times nothing)
+            L.lnbnn_autotune(ix, dq, off, args.k, mode, cache_path=TUNING_CACHE)
         L.lnbnn_classify(ix, dq, off, args.k, mode, flags=L.LNBNN_TIMING, out=out)
-        t = L.lnbnn_last_timing(ix)
-        k1_ms.append(t["dist_kernel_ms"])
-        tot_ms.append(t["total_ms"])
-        log(f"fp8 step {i + 1}/{steps}: candidate pass {k1_ms[-1]:.1f} ms, whole sequence {tot_ms[-1]:.1f} ms")
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    n_q = int(Q.shape[0])
-    acc = float(np.mean(out["class"].cpu().numpy() == true_cls))
-    k1 = float(np.mean(k1_ms)) / 1e3
-    flop = 2.0 * 128 * cfg.n_refs * n_q
-    achieved = flop / k1 / 1e12
-    del R
-    return {
-        "metric": "query descriptors/s at 15.4M refs k=10 (FP8 candidates + exact FP32 re-rank)",
-        "value": n_q * steps / dt, "unit": "query descriptors/s", "steps": steps,
-        "ms_per_step": dt / steps * 1e3, "dtype": "fp8 e4m3 -> f32",
-        "config": {"workload": "P: 15.36M float32 refs (L structure, unit-norm ReLU descriptors, noise 0.08), "
-                               f"{n_q} query descriptors in 512 images; k={args.k}, 4k candidates",
-                   "variant": L.lnbnn_variant_name(L.lnbnn_last_timing(ix)["tile_variant"]),
-                   "autotuned": tuned},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_FP8_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_MFMA_FP8_TFLOPS, "kernel": "k_dist_topk (FP8 candidate pass)",
-                     "kernel_ms": k1 * 1e3, "sequence_ms": float(np.mean(tot_ms))},
-        "quality": "recall against the FP64 oracle is checked at this size by the GPU tests "
-                   "(sampled descriptors and one whole image), not timed here",
-        "accuracy_statistic": acc,
-    }, ix
+        torch.cuda.synchronize()
+        steps = max(1, min(args.steps, 3))
+        t0 = time.perf_counter()
+        k1_ms, tot_ms = [], []
+        for i in range(steps):
+            L.lnbnn_classify(ix, dq, off, args.k, mode, flags=L.LNBNN_TIMING, out=out)
+            t = L.lnbnn_last_timing(ix)
+            k1_ms.append(t["dist_kernel_ms"])
+            tot_ms.append(t["total_ms"])
+            log(f"fp8 mode {mode} step {i + 1}/{steps}: candidate pass {k1_ms[-1]:.1f} ms, "
+                f"whole sequence {tot_ms[-1]:.1f} ms")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        acc = float(np.mean(out["class"].cpu().numpy() == true_cls))
+        k1 = float(np.mean(k1_ms)) / 1e3
+        achieved = flop / k1 / 1e12
+        legs[mode] = {
+            "metric": "query descriptors/s at 15.4M refs k=10 (FP8 candidates + exact FP32 re-rank)",
+            "value": n_q * steps / dt, "unit": "query descriptors/s", "steps": steps,
+            "ms_per_step": dt / steps * 1e3, "dtype": "fp8 e4m3 -> f32",
+            "config": {"workload": "P: 15.36M float32 refs (L structure, unit-norm ReLU descriptors, noise 0.08), "
+                                   f"{n_q} query descriptors in 512 images; k={args.k}, 4k candidates ({name})",
+                       "variant": L.lnbnn_variant_name(L.lnbnn_last_timing(ix)["tile_variant"]),
+                       "autotuned": tuned},
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_FP8_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_MFMA_FP8_TFLOPS, "kernel": "k_dist_topk (FP8 candidate pass)",
+                         "kernel_ms": k1 * 1e3, "sequence_ms": float(np.mean(tot_ms))},
+            "quality": fp8_quality(L, torch, np, ix, dq, off, args.k, mode, cfg.n_classes),
+            "accuracy_statistic": acc,
+        }
+        log(f"fp8 mode {mode}: quality {legs[mode]['quality']}")
+    return legs[FP8], legs[FP8_2K], ix
 
 
 def serving_leg(args, L, torch, np, synth, ix_exact, ix_fp8, mu_exact_qps, out=None):
@@ -382,28 +470,32 @@ def serving_leg(args, L, torch, np, synth, ix_exact, ix_fp8, mu_exact_qps, out=N
 
 
 def class_sweep_leg(args, L, torch, np, synth):
-    """Exact path as the number of classes grows at a fixed 30 x 2000
+    """Local NBNN (exact, INT8) and the original NBNN rule (Algorithm 1, on
+    the same tiles) as the number of classes grows at a fixed 30 x 2000
     references per class (64 query images of the same size mix per point):
-    the shape of the paper's class-count experiment (Fig. 5).  Exact search
-    is linear in the number of references; the paper's approximate index
-    grows with its logarithm."""
+    the two curves of the paper's class-count experiment (Fig. 5).  With
+    exact search both rules visit every reference, so both are linear in the
+    number of references; the paper's 100x gap belongs to its approximate
+    per-class indexes."""
     base = synth.CONFIGS["L"]
     rows = []
+    I8, NB = L.LNBNN_EXACT_I8, L.LNBNN_NBNN_I8
     for nc in (2, 8, 32, 128, 256):
         cfg = synth.scaled(base, n_classes=nc, n_img=64)
         R, labels = synth.gen_index(cfg)
         Q, off, true_cls = synth.gen_queries(cfg)
-        ix = L.lnbnn_build_index(R, labels, nc, L.LNBNN_MODE_BIT(L.LNBNN_EXACT_I8))
+        ix = L.lnbnn_build_index(R, labels, nc, L.LNBNN_MODE_BIT(I8) | L.LNBNN_MODE_BIT(NB))
         del R
         dq = torch.from_numpy(Q).cuda()
-        dt, k1, _, cls = time_exact(args, L, torch, np, ix, dq, off, nc, L.LNBNN_EXACT_I8, 2, 1)
-        ix.free()
         n_q = int(Q.shape[0])
-        rows.append({"n_classes": nc, "n_refs": cfg.n_refs, "query_desc": n_q,
-                     "query_desc_per_s": n_q / dt, "ms_per_image": dt * 1e3 / 64,
-                     "dist_kernel_ms": k1,
-                     "dist_kernel_ops_per_s": 2.0 * 128 * cfg.n_refs * n_q / (k1 / 1e3),
-                     "accuracy_statistic": float(np.mean(cls == true_cls))})
+        row = {"n_classes": nc, "n_refs": cfg.n_refs, "query_desc": n_q}
+        for mode, name in ((I8, "local_nbnn"), (NB, "nbnn_original")):
+            dt, k1, _, cls = time_exact(args, L, torch, np, ix, dq, off, nc, mode, 2, 1)
+            row[name] = {"query_desc_per_s": n_q / dt, "ms_per_image": dt * 1e3 / 64, "dist_kernel_ms": k1,
+                         "dist_kernel_ops_per_s": 2.0 * 128 * cfg.n_refs * n_q / (k1 / 1e3),
+                         "accuracy_statistic": float(np.mean(cls == true_cls))}
+        ix.free()
+        rows.append(row)
         log(f"class sweep: {rows[-1]}")
     return rows
 
@@ -449,7 +541,7 @@ def main():
     ix8 = None
     if "fp8" in legs:
         try:
-            res["fp8_rerank"], ix8 = fp8_leg(args, L, torch, np, synth)
+            res["fp8_rerank"], res["fp8_rerank_2k"], ix8 = fp8_leg(args, L, torch, np, synth)
         except Exception as e:  # the headline line must still be printed
             res["fp8_rerank"] = {"error": repr(e)}
     if "serving" in legs and ix8 is not None and "error" not in res.get("serving", {}):

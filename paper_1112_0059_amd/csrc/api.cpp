@@ -398,6 +398,7 @@ int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t
         r.upd_cls = io.upd_cls;
         r.upd_delta = io.upd_delta;
         r.totals_f64 = io.totals_f64;
+        r.status = w->status;
         LN_HIP(launch_rerank(r, io.q_cap, io.img_cap, s));
     } else if (nbnn) {
         NbnnArgs n{};
@@ -425,6 +426,7 @@ int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t
         f.part_d = io.part_d;
         f.part_i = io.part_i;
         f.totals = io.totals;
+        f.status = w->status;
         LN_HIP(launch_finish(f, io.q_cap, s));
         LN_HIP(launch_argmin(io.totals, io.bd, io.img_cap, ix->n_classes, s));
     }
@@ -756,10 +758,11 @@ int lnbnn::validate_classify(const lnbnn_index *ix, const void *queries, int dty
 
 std::string lnbnn::graph_key(const Plan &p, const BatchIO &io)
 {
-    // the plan, the capacities and the workspace buffers; the caller's
+    // the plan, the capacities, the workspace buffers and the stage-wait
+    // bound (all kernel arguments frozen into the graph); the caller's
     // queries and outputs travel in the batch descriptor
     std::ostringstream o;
-    o << p.variant << '/' << p.fmt << '/' << p.kpb << '/' << p.n_slices << '/' << p.tiles_per_slice << '/' << p.chunk_tiles << '/'
+    o << wait_spin_limit() << '/' << p.variant << '/' << p.fmt << '/' << p.kpb << '/' << p.n_slices << '/' << p.tiles_per_slice << '/' << p.chunk_tiles << '/'
       << p.grid << '/' << io.q_cap << '/' << io.img_cap << '/' << io.k << '/' << io.mode << '/' << io.offsets << '/'
       << io.bd << '/' << io.totals << '/' << io.totals_f64 << '/' << io.part_d << '/' << io.part_i << '/' << io.q8
       << '/' << io.cand;

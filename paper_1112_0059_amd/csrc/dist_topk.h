@@ -667,11 +667,15 @@ static __device__ __forceinline__ void pipe_step_regs(typename Op::acc_t (&acc_n
         if (__builtin_expect(any[nt], 0)) tile_insert<Op, KP>(acc_old[nt], thr[nt], gt[nt], ld[nt], li[nt], row_old, h, parity);
 }
 
+// Two waves per SIMD (256 registers each), except where the lists need one
+// wave per SIMD (W = 4) and its full register file: the 64-entry lists, and
+// two query tiles of lists longer than 20.
+template <int KP, int NT>
+constexpr int waves_per_simd() { return (KP > 40 || (NT == 2 && KP > 20)) ? 1 : 2; }
+
 template <class Op, int KP, int NT, int MT, int W, int NB>
-// Two waves per SIMD (256 registers each), except the 64-entry lists, which
-// need one wave per SIMD (W = 4) and its full register file.
 __global__ __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W),
-                          amdgpu_waves_per_eu(KP > 40 ? 1 : 2, KP > 40 ? 1 : 2)))
+                          amdgpu_waves_per_eu(waves_per_simd<KP, NT>(), waves_per_simd<KP, NT>())))
 void k_dist_topk(DistArgs a)
 {
     constexpr int S = Op::kSteps;
@@ -708,20 +712,16 @@ void k_dist_topk(DistArgs a)
         if ((threadIdx.x & 63) == 0)
             __hip_atomic_fetch_add(&s_cnt[i], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     };
-    // Bounded wait: after spin_limit sleep rounds the wave gives up and
-    // reports it in the status word (lane 0, a vector atomic), which the
-    // host turns into an error for the call, so a miscount can neither hang
-    // the GPU nor pass unnoticed.
-    auto cnt_wait = [&](int i, uint32_t target) {
+    // Bounded wait: after spin_limit sleep rounds the wave stops waiting and
+    // the call returns true (see mark_if for how that is reported).
+    auto cnt_wait = [&](int i, uint32_t target) -> bool {
         int it = 0;
-        while (__hip_atomic_load(&s_cnt[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
-            if (++it > a.spin_limit) {
-                if ((threadIdx.x & 63) == 0) atomicOr(a.status, kStatusWaitGaveUp);
-                break;
-            }
+        for (; it < a.spin_limit; ++it) {
+            if (__hip_atomic_load(&s_cnt[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= target) break;
             __builtin_amdgcn_s_sleep(1);
         }
         asm volatile("" ::: "memory");
+        return it >= a.spin_limit;
     };
 
     const int tid = threadIdx.x;
@@ -776,12 +776,24 @@ void k_dist_topk(DistArgs a)
                 thr[nt] = ld[nt][KP - 1];
                 gt[nt] = Op::gate_thr(thr[nt]);
             }
+            // A wave whose stage wait gave up marks its first list with a NaN
+            // key in the last slot: its threshold turns NaN, so nothing more
+            // is inserted, and the kernels that read the lists (merge, FP8
+            // candidate merge, the per-class flush below) turn the mark into
+            // the call's error.  The mark lives in registers that are live
+            // anyway: a flag of its own made the hot loop spill.
+            auto mark_if = [&](bool gave_up) {
+                const float nan = __builtin_nanf("");
+                ld[0][KP - 1] = gave_up ? nan : ld[0][KP - 1];
+                thr[0] = gave_up ? nan : thr[0];
+            };
             // Original NBNN: the class of the entries now in the lists, and
             // their flush into the per-class minima.
             int cur_cls = 0;
             if constexpr (Op::kNbnn) cur_cls = a.tile_class[t0];
             auto nbnn_flush = [&]() {
                 if constexpr (Op::kNbnn) {
+                    if (__builtin_isnan(ld[0][KP - 1]) && lane == 0) atomicOr(a.status, kStatusWaitGaveUp);
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt) {
                         if (qi[nt] < n_q && ld[nt][0] < __builtin_inff())
@@ -821,7 +833,7 @@ void k_dist_topk(DistArgs a)
             wait_vmcnt<(PF - 1) * LPS>();
             if constexpr (kCounters) {
                 cnt_signal(0);                  // this wave's share of stage 0 has landed
-                cnt_wait(0, W);
+                mark_if(cnt_wait(0, W));
             } else {
                 __syncthreads();
             }
@@ -848,13 +860,20 @@ void k_dist_topk(DistArgs a)
                 // is in registers.
                 TileRegs<Op> tr[2];           // tile m lives in tr[m % 2]
                 tile_load<Op>(s_frag[0], s_seed[0], s_rsc[0], lane, h, tr[0]);
+                // original NBNN: the class of stage st + 1 is loaded during
+                // stage st and read after the stage's last LDS wait, so the
+                // scalar load never adds a wait of its own
+                int st_cls = cur_cls, nx_cls = cur_cls;
                 for (int st = 0; st < n_st; ++st) {
-                    int st_cls = 0;
-                    if constexpr (Op::kNbnn) st_cls = a.tile_class[t0 + (int64_t)st * MT];
+                    int ld_cls = 0;
+                    if constexpr (Op::kNbnn) {
+                        st_cls = nx_cls;
+                        ld_cls = a.tile_class[t0 + (int64_t)min(st + 1, n_st - 1) * MT];
+                    }
                     {
                         const int sn = st + PF;
                         const int nb = sn % NB;
-                        cnt_wait(NB + nb, (uint32_t)(W * (sn / NB)));
+                        mark_if(cnt_wait(NB + nb, (uint32_t)(W * (sn / NB))));
                         const int64_t ts = t0 + (int64_t)(sn < n_st ? sn : 0) * MT;
                         stage_copy<Op, MT, W, TILE_U4>(a.frag + ts * TILE_U4, s_frag[nb], a.seed + ts * kTileRows,
                                                        reinterpret_cast<float *>(s_seed[nb]),
@@ -869,9 +888,10 @@ void k_dist_topk(DistArgs a)
                         }
                         if constexpr (m == MT - 1) {
                             __builtin_amdgcn_s_waitcnt(0xc07f); // lgkmcnt(0): this wave's reads of stage st done
+                            if constexpr (Op::kNbnn) nx_cls = ld_cls;
                             cnt_signal(NB + st % NB);
                             const int nb = (st + 1) % NB;
-                            cnt_wait(nb, (uint32_t)(W * ((st + 1) / NB + 1)));
+                            mark_if(cnt_wait(nb, (uint32_t)(W * ((st + 1) / NB + 1))));
                             tile_load<Op>(s_frag[nb], s_seed[nb], s_rsc[nb], lane, h, tr[(m + 1) % 2]);
                         } else {
                             tile_load<Op>(s_frag[st % NB] + (m + 1) * TILE_U4, s_seed[st % NB] + (m + 1) * 8,
@@ -902,9 +922,13 @@ void k_dist_topk(DistArgs a)
                 // tile can be loaded while that last tile computes.
                 TileRegs<Op> tr[2];           // tile m lives in tr[m % 2]
                 tile_load<Op>(s_frag[0], s_seed[0], s_rsc[0], lane, h, tr[0]);
+                int st_cls = cur_cls, nx_cls = cur_cls;   // as in the counter path above
                 for (int st = 0; st < n_st; ++st) {
-                    int st_cls = 0;
-                    if constexpr (Op::kNbnn) st_cls = a.tile_class[t0 + (int64_t)st * MT];
+                    int ld_cls = 0;
+                    if constexpr (Op::kNbnn) {
+                        st_cls = nx_cls;
+                        ld_cls = a.tile_class[t0 + (int64_t)min(st + 1, n_st - 1) * MT];
+                    }
                     {   // stage st + PD goes into the buffer stage st - 1 used
                         const int sn = st + PD;
                         const int64_t ts = t0 + (int64_t)(sn < n_st ? sn : 0) * MT;
@@ -919,6 +943,7 @@ void k_dist_topk(DistArgs a)
                         if constexpr (m == MT - 1) {
                             wait_vmcnt<(PD - 1) * LPS>();       // stage st + 1 landed (this wave's part)
                             __builtin_amdgcn_s_waitcnt(0xc07f); // lgkmcnt(0): this wave's reads of stage st done
+                            if constexpr (Op::kNbnn) nx_cls = ld_cls;
                             asm volatile("" ::: "memory");
                             __builtin_amdgcn_s_barrier();
                             asm volatile("" ::: "memory");
@@ -1029,6 +1054,9 @@ static void *pick_variant(int v)
         // 8-tile stages for one query tile per wave (the longer lists): 4 KB tiles
         if constexpr (KP <= 40 && Op::kSteps * Op::kAU == 4)
             if (v == 11) return kernel_ptr<Op, KP, 1, 8, 8, 3>();
+        // two query tiles of long lists, one wave per SIMD: FP8 candidate lists
+        if constexpr (Op::kFmt == FMT_FP8 && KP > 20)
+            if (v == 12) return kernel_ptr<Op, KP, 2, 8, 4, 3>();
         if constexpr (Op::kFmt == FMT_FP8) {
             if constexpr (KP <= 20) {
                 switch (v) {

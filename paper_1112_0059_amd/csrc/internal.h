@@ -58,7 +58,8 @@ struct DistArgs {
     int64_t q_cap;              // capacity: part buffers are laid out for q_cap queries
     float *part_d;              // [n_slices * 2][q_cap][kp]
     int32_t *part_i;
-    int32_t *status;            // bit 0 set by a wave whose bounded stage wait gave up
+    int32_t *status;            // bit 0: a bounded stage wait gave up (set by the kernels that
+                                // read the lists, which carry the mark as a NaN key)
     int32_t spin_limit;         // sleep rounds a stage wait allows before it gives up
     // original NBNN (FMT_I8N): class of every 32-row tile, and the per-class
     // minimum key of every query, [n_classes][q_cap] (atomic minima)
@@ -96,6 +97,7 @@ struct RerankArgs {
     int32_t *upd_cls;           // [q_cap, k]: class of the update of rank j, -1 if none
     double *upd_delta;          // [q_cap, k]
     double *totals_f64;         // [n_img, n_classes]
+    int32_t *status;            // set when a list carries a stage-wait mark
 };
 
 struct FinishArgs {
@@ -114,6 +116,7 @@ struct FinishArgs {
     const float *part_d;
     const int32_t *part_i;
     unsigned long long *totals; // [n_img, n_classes] int64 (two's complement)
+    int32_t *status;            // set when a list carries a stage-wait mark
 };
 
 // number of kernel variants and their parameters

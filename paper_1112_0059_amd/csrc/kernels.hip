@@ -125,7 +125,13 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs a)
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n_q;
          q += (int64_t)gridDim.x * blockDim.x) {
         int heads[64];
-        for (int l = 0; l < a.n_lists; ++l) heads[l] = 0;
+        bool marked = false;            // a list's last key is NaN: its stage wait gave up
+        for (int l = 0; l < a.n_lists; ++l) {
+            heads[l] = 0;
+            const float last = a.part_d[((int64_t)l * a.q_cap + q) * a.kp_stride + a.kp_stride - 1];
+            marked = marked || __builtin_isnan(last);
+        }
+        if (marked) atomicOr(a.status, kStatusWaitGaveUp);
         float dd[kMaxKP];
         int ii[kMaxKP];
         for (int p = 0; p < kp; ++p) {
@@ -305,10 +311,12 @@ static const Variant kVariants[] = {
     {2, 4, 8, 8},   // 9  (4 KB tiles only: INT8, FP8)
     {2, 8, 8, 3},   // 10 (160-element INT8 rows only)
     {1, 8, 8, 3},   // 11 (8-bit formats: INT8 rows of 128 or 160, FP8 lists up to 40)
+    {2, 8, 4, 3},   // 12 (FP8 lists of 40 and 64: one wave per SIMD)
 };
 static const char *kVariantNames[] = {"w4_nt1_mt2_nb4", "w4_nt2_mt2_nb4", "w4_nt2_mt4_nb2", "w4_nt2_mt2_nb2",
                                       "w8_nt2_mt4_nb4", "w8_nt2_mt2_nb8", "w8_nt1_mt4_nb4", "w4_nt2_mt4_nb3",
-                                      "w8_nt2_mt8_nb4", "w8_nt2_mt4_nb8", "w8_nt2_mt8_nb3", "w8_nt1_mt8_nb3"};
+                                      "w8_nt2_mt8_nb4", "w8_nt2_mt4_nb8", "w8_nt2_mt8_nb3", "w8_nt1_mt8_nb3",
+                                      "w4_nt2_mt8_nb3"};
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int num_variants() { return kNumVariants; }
@@ -339,6 +347,7 @@ bool variant_supports(int v, int fmt, int kp)
     // in these stage shapes
     if (fmt == FMT_I8L) return v == 11 || ((v == 2 || v == 7 || v == 10) && b <= 16);
     if (v == 10) return false;
+    if (v == 12) return fmt == FMT_FP8 && b > 20;
     // one query tile per wave with 8-tile stages: the 4 KB-tile formats
     if (v == 11) return fmt == FMT_I8 || fmt == FMT_I8N || (fmt == FMT_FP8 && b <= 40);
     // the deep stage variants need the 4 KB tiles of the 8-bit formats

@@ -139,7 +139,13 @@ __global__ __launch_bounds__(256) void k_cand_merge(RerankArgs a)
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n_q;
          q += (int64_t)gridDim.x * blockDim.x) {
         int heads[64];
-        for (int l = 0; l < a.n_lists; ++l) heads[l] = 0;
+        bool marked = false;            // a list's last key is NaN: its stage wait gave up
+        for (int l = 0; l < a.n_lists; ++l) {
+            heads[l] = 0;
+            const float last = a.part_d[((int64_t)l * a.q_cap + q) * a.kp_stride + a.kp_stride - 1];
+            marked = marked || __builtin_isnan(last);
+        }
+        if (marked) atomicOr(a.status, kStatusWaitGaveUp);
         for (int p = 0; p < a.n_cand; ++p) {
             float bd = __builtin_inff();
             int bi = -1, bl = 0;
@@ -215,12 +221,17 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a)
         }
         const unsigned long long m0 = __builtin_amdgcn_ballot_w64(rank[0] == k);
         const unsigned long long m1 = __builtin_amdgcn_ballot_w64(nc > 1 && rank[1] == k);
-        const float db = m0 ? __shfl(d[0], (int)__builtin_ctzll(m0)) : __shfl(d[1], (int)__builtin_ctzll(m1));
+        // the holder of rank k (always one with valid lists; lane 0 otherwise)
+        const int src = m0 ? (int)__builtin_ctzll(m0) : m1 ? (int)__builtin_ctzll(m1) : 0;
+        const float db = m0 ? __shfl(d[0], src) : __shfl(d[1], src);
         int cls[2];
         bool first[2];
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            first[c] = c < nc && rank[c] < k;
+            // a slot without a real candidate (only possible when the lists
+            // are invalid, e.g. after a stage wait gave up) never reads a label
+            const bool real = idx[c] >= 0 && idx[c] < a.n_refs;
+            first[c] = c < nc && rank[c] < k && real;
             cls[c] = first[c] ? a.labels[idx[c]] : -1;
         }
         for (int c2 = 0; c2 < nc; ++c2) {

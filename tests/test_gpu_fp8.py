@@ -184,7 +184,7 @@ def test_fp8_alone_equals_in_mix(small):
         assert np.array_equal(alone[2], batch[2][s:e]) and np.array_equal(alone[3], batch[3][s:e])
 
 
-@pytest.mark.parametrize("variant", [0, 6])
+@pytest.mark.parametrize("variant", [0, 6, 11, 12])
 def test_fp8_variants_and_chunks(small, variant):
     cfg, R, labels, Q, off, ix, want = small
     base = L.lnbnn_classify(ix, Q, off, 10, FP8, want_neighbours=True)

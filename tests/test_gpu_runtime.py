@@ -75,6 +75,32 @@ def test_wait_that_gives_up_is_reported(tiny):
         ix.free()
 
 
+@pytest.mark.parametrize("mode", [L.LNBNN_FP8_RERANK, L.LNBNN_NBNN_I8])
+def test_wait_that_gives_up_is_reported_other_modes(tiny, mode):
+    """The same for the FP8 candidate pass (the candidate merge reads the
+    mark) and the original NBNN rule (its per-class flush reads it)."""
+    cfg, R, labels, Q, off, _ = tiny
+    if mode == L.LNBNN_FP8_RERANK:
+        R = (R.astype(np.float32) + 1.0) / 256.0
+        Q = (Q.astype(np.float32) + 1.0) / 256.0
+    ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(mode))
+    try:
+        L.lnbnn_set_variant(ix, mode, 10, 11 if mode == L.LNBNN_FP8_RERANK else 8)
+        want = L.lnbnn_classify(ix, Q, off, 10, mode)
+        os.environ["LNBNN_WAIT_SPINS"] = "0"
+        try:
+            _say(f"mode {mode}, zero wait bound")
+            with pytest.raises(L.LnbnnError) as e:
+                L.lnbnn_classify(ix, Q, off, 10, mode)
+            assert e.value.code == L.LNBNN_EDEVICE
+        finally:
+            del os.environ["LNBNN_WAIT_SPINS"]
+        got = L.lnbnn_classify(ix, Q, off, 10, mode)
+        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+    finally:
+        ix.free()
+
+
 def test_graph_cache_bounded_and_exact(tiny):
     """Twelve launch shapes (k = 1..12) through the default graph path: more
     than the cache keeps, so entries are evicted and recaptured; every call
