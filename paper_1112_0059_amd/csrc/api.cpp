@@ -298,16 +298,18 @@ int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_varia
     if (!variant_supports(v, fmt, kp))
         return set_err(LNBNN_EINVAL, "variant %d cannot serve mode %d with k + 1 = %d", v, mode, kp);
     const Variant var = variant(v);
-    const int64_t qb = (int64_t)var.waves * 32 * var.nt;
+    const int64_t qb = (int64_t)var.waves * var.qt * var.nt;
+    const int groups = 64 / var.qt;              // lists per query and slice
     const int64_t n_qb = std::max<int64_t>(1, (q_cap + qb - 1) / qb);
     const int64_t n_tiles = ix->rows[fmt] / kTileRows;
     const int bpc = blocks_per_cu(ix, v, fmt, kpb);
     int64_t resident = (int64_t)ix->cu_count * bpc;
     if (tu.max_workgroups > 0) resident = std::min<int64_t>(resident, tu.max_workgroups);
     // Split the reference set only when the query blocks alone cannot keep
-    // every workgroup slot busy; each split costs one more partial list.
+    // every workgroup slot busy; each split costs one more partial list per
+    // lane group (the merge takes at most 64 lists per query).
     int64_t want = 1;
-    if (n_qb < 2 * resident) want = std::min<int64_t>(32, (2 * resident + n_qb - 1) / n_qb);
+    if (n_qb < 2 * resident) want = std::min<int64_t>(64 / groups, (2 * resident + n_qb - 1) / n_qb);
     int64_t tps = (n_tiles + want - 1) / want;
     tps = std::max<int64_t>(8, (tps + 7) / 8 * 8);
     const int64_t S = (n_tiles + tps - 1) / tps;
@@ -315,6 +317,7 @@ int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_varia
     out->fmt = fmt;
     out->kpb = kpb;
     out->n_slices = (int)S;
+    out->n_lists = (int)S * groups;
     out->tiles_per_slice = (int)tps;
     out->grid = (int)std::max<int64_t>(1, std::min<int64_t>(n_qb * S, resident));
     // By default an item sweeps its whole slice with its lists in registers;
@@ -326,7 +329,7 @@ int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_varia
     return LNBNN_OK;
 }
 
-int64_t part_elems(const Plan &p, int64_t q_cap) { return (int64_t)p.n_slices * 2 * q_cap * p.kpb; }
+int64_t part_elems(const Plan &p, int64_t q_cap) { return (int64_t)p.n_lists * q_cap * p.kpb; }
 
 int64_t work_elems(const lnbnn_index *ix, const Plan &p, int64_t q_cap)
 {
@@ -386,7 +389,7 @@ int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t
         r.ref_f32 = ix->ref_f32;
         r.labels = ix->labels;
         r.n_refs = ix->n_refs;
-        r.n_lists = 2 * p.n_slices;
+        r.n_lists = p.n_lists;
         r.kp_stride = p.kpb;
         r.n_cand = fp8_candidates(io.k);
         r.k = io.k;
@@ -418,7 +421,7 @@ int enqueue_batch(lnbnn_index *ix, const Plan &p, const BatchIO &io, hipStream_t
         f.offsets = io.offsets;
         f.labels = ix->labels;
         f.n_refs = ix->n_refs;
-        f.n_lists = 2 * p.n_slices;
+        f.n_lists = p.n_lists;
         f.kp_stride = p.kpb;
         f.k = io.k;
         f.n_classes = ix->n_classes;

@@ -13,6 +13,7 @@
 // BF16 operands with FP32 accumulation are exact in any summation order.
 #pragma once
 #include "internal.h"
+#include <type_traits>
 
 namespace lnbnn {
 
@@ -22,6 +23,8 @@ typedef int i32x4v __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4v __attribute__((ext_vector_type(4)));
 
 static __device__ __forceinline__ uint32_t byte_at(uint2 r, int e)
 {
@@ -68,12 +71,32 @@ static __device__ __forceinline__ int min16(const i32x16 &a)
     return min(min(mn, m4), a[15]);
 }
 
+static __device__ __forceinline__ float min8(const f32x8 &a)
+{
+    const float m0 = __builtin_fminf(__builtin_fminf(a[0], a[1]), __builtin_fminf(a[2], a[3]));
+    const float m1 = __builtin_fminf(__builtin_fminf(a[4], a[5]), __builtin_fminf(a[6], a[7]));
+    return __builtin_fminf(m0, m1);
+}
+
+static __device__ __forceinline__ int min8(const i32x8 &a)
+{
+    return min(min(min(a[0], a[1]), min(a[2], a[3])), min(min(a[4], a[5]), min(a[6], a[7])));
+}
+
 // Float formats: the accumulator is the ranking key d' itself.  The gate
 // compares a tile's smallest key with the list's KP-th key.
 struct FloatKeys {
     static constexpr int kRow = kDim;     // elements per descriptor
     static constexpr bool kNbnn = false;  // per-class minima (original NBNN) instead of k+1 lists
+    // 32x32 output blocks: lanes l and l+32 share query column l & 31; each
+    // holds 16 rows of a tile, register r being row 8*(r/4) + 4*(l/32) + r%4
+    static constexpr int kQT = 32;        // query columns per MFMA
+    static constexpr int kGroups = 2;     // lanes (and so lists) per query
+    static constexpr int kAccN = 16;      // accumulator registers per tile and query tile
+    static constexpr int kRowStride = 8;  // row distance between register groups of four
+    static constexpr int kMfma = 1;       // MFMA instructions per K step
     using acc_t = f32x16;
+    using seed_t = f32x16;
     using gate_t = float;
     static constexpr bool kParity = false;
     static __device__ __forceinline__ float init() { return __builtin_inff(); }
@@ -90,6 +113,7 @@ struct OpF16 : FloatKeys {
     static constexpr int kFmt = FMT_F16;
     static constexpr int kSteps = 8;
     static constexpr int kAU = 1;          // uint4 per lane per step
+    static constexpr int kBU = 1;          // query uint4 per lane per step
     static constexpr bool kScaled = false;
     static __device__ __forceinline__ uint4 cvt8(uint2 raw, float mul)
     {
@@ -99,7 +123,7 @@ struct OpF16 : FloatKeys {
         return __builtin_bit_cast(uint4, v);
     }
     static __device__ __forceinline__ void load_b(const void *q, const int32_t *, int64_t qi, bool ok, int h,
-                                                  uint4 (&b)[kSteps][kAU], int &sb)
+                                                  uint4 (&b)[kSteps][kBU], int &sb)
     {
         const uint8_t *qrow = static_cast<const uint8_t *>(q) + (ok ? qi : 0) * kDim + 8 * h;
 #pragma unroll
@@ -117,7 +141,7 @@ struct OpF16 : FloatKeys {
         if (ok) raw = *reinterpret_cast<const uint2 *>(row + 16 * s + 8 * h);
         return cvt8(raw, 1.0f);
     }
-    static __device__ __forceinline__ f32x16 mma(const uint4 (&a)[kAU], const uint4 (&b)[kAU], f32x16 c, int, int)
+    static __device__ __forceinline__ f32x16 mma(const uint4 (&a)[kAU], const uint4 (&b)[kBU], f32x16 c, int, int)
     {
         return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a[0]),
                                                       __builtin_bit_cast(f16x8, b[0]), c, 0, 0, 0);
@@ -128,6 +152,7 @@ struct OpBF16 : FloatKeys {
     static constexpr int kFmt = FMT_BF16;
     static constexpr int kSteps = 8;
     static constexpr int kAU = 1;
+    static constexpr int kBU = 1;
     static constexpr bool kScaled = false;
     static __device__ __forceinline__ uint4 cvt8(uint2 raw, float mul)
     {
@@ -137,7 +162,7 @@ struct OpBF16 : FloatKeys {
         return __builtin_bit_cast(uint4, v);
     }
     static __device__ __forceinline__ void load_b(const void *q, const int32_t *, int64_t qi, bool ok, int h,
-                                                  uint4 (&b)[kSteps][kAU], int &sb)
+                                                  uint4 (&b)[kSteps][kBU], int &sb)
     {
         const uint8_t *qrow = static_cast<const uint8_t *>(q) + (ok ? qi : 0) * kDim + 8 * h;
 #pragma unroll
@@ -155,7 +180,7 @@ struct OpBF16 : FloatKeys {
         if (ok) raw = *reinterpret_cast<const uint2 *>(row + 16 * s + 8 * h);
         return cvt8(raw, 1.0f);
     }
-    static __device__ __forceinline__ f32x16 mma(const uint4 (&a)[kAU], const uint4 (&b)[kAU], f32x16 c, int, int)
+    static __device__ __forceinline__ f32x16 mma(const uint4 (&a)[kAU], const uint4 (&b)[kBU], f32x16 c, int, int)
     {
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[0]),
                                                        __builtin_bit_cast(bf16x8, b[0]), c, 0, 0, 0);
@@ -166,10 +191,11 @@ struct OpFP8 : FloatKeys {
     static constexpr int kFmt = FMT_FP8;
     static constexpr int kSteps = 2;
     static constexpr int kAU = 2;
+    static constexpr int kBU = 2;
     static constexpr bool kScaled = true;
     // queries: FP8 codes [n_q][128] in natural K order, E8M0 scale per query
     static __device__ __forceinline__ void load_b(const void *q, const int32_t *qsc, int64_t qi, bool ok, int h,
-                                                  uint4 (&b)[kSteps][kAU], int &sb)
+                                                  uint4 (&b)[kSteps][kBU], int &sb)
     {
         const uint4 *qrow = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(q) + (ok ? qi : 0) * kDim);
 #pragma unroll
@@ -178,7 +204,7 @@ struct OpFP8 : FloatKeys {
             for (int u = 0; u < kAU; ++u) b[s][u] = ok ? qrow[4 * s + 2 * h + u] : make_uint4(0u, 0u, 0u, 0u);
         sb = ok ? qsc[qi] : 127;
     }
-    static __device__ __forceinline__ f32x16 mma(const uint4 (&a)[kAU], const uint4 (&b)[kAU], f32x16 c, int sa,
+    static __device__ __forceinline__ f32x16 mma(const uint4 (&a)[kAU], const uint4 (&b)[kBU], f32x16 c, int sa,
                                                  int sb)
     {
         i32x8 av, bv;
@@ -215,8 +241,15 @@ struct OpI8T {
     static constexpr int kSteps = S;
     static constexpr int kRow = 32 * S;      // bytes per descriptor
     static constexpr int kAU = 1;
+    static constexpr int kBU = 1;
     static constexpr bool kScaled = false;
+    static constexpr int kQT = 32;           // as for the float formats
+    static constexpr int kGroups = 2;
+    static constexpr int kAccN = 16;
+    static constexpr int kRowStride = 8;
+    static constexpr int kMfma = 1;
     using acc_t = i32x16;
+    using seed_t = f32x16;
     using gate_t = int;
     static constexpr bool kParity = true;
     static constexpr int kPadSeed = 1 << 30;
@@ -239,7 +272,7 @@ struct OpI8T {
         return d >= (1 << 29) ? __builtin_inff() : (float)(2 * d + (int)((parity >> row) & 1u));
     }
     static __device__ __forceinline__ void load_b(const void *q, const int32_t *, int64_t qi, bool ok, int h,
-                                                  uint4 (&b)[kSteps][kAU], int &sb)
+                                                  uint4 (&b)[kSteps][kBU], int &sb)
     {
         const uint4 *qrow = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(q) + (ok ? qi : 0) * kRow);
 #pragma unroll
@@ -260,7 +293,7 @@ struct OpI8T {
         const uint32_t m = 0x80808080u;
         return make_uint4(v.x ^ m, v.y ^ m, v.z ^ m, v.w ^ m);
     }
-    static __device__ __forceinline__ i32x16 mma(const uint4 (&a)[kAU], const uint4 (&b)[kAU], i32x16 c, int, int)
+    static __device__ __forceinline__ i32x16 mma(const uint4 (&a)[kAU], const uint4 (&b)[kBU], i32x16 c, int, int)
     {
         return __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(i32x4v, a[0]), __builtin_bit_cast(i32x4v, b[0]),
                                                      c, 0, 0, 0);
@@ -270,22 +303,147 @@ using OpI8 = OpI8T<4, FMT_I8>;
 using OpI8L = OpI8T<5, FMT_I8L>;
 using OpI8N = OpI8T<4, FMT_I8N, true>;
 
+// 16x16 output blocks (v_mfma_i32_16x16x64_i8, v_mfma_f32_16x16x32_{f16,bf16}).
+// A 32-row tile is two 16-row blocks b = 0, 1; lane l holds query column
+// l & 15, and register 4b + i is row 16b + 4*(l/16) + i, so four lanes (and
+// four lists) share each query.  Each block MFMA reads K elements
+// K0 + 16*(l/16) + e (INT8, e < 16) or K0 + 8*(l/16) + e (16-bit, e < 8) of
+// row 16b + (l & 15): in the 32x32 packing that chunk sits in K step
+// 2 s + (l/16)/2, lane 16 b + (l & 15) + 32 ((l/16) & 1), so both shapes read
+// the same packed index.
+template <class Op>
+static __device__ __forceinline__ int frag_off(int s, int u, int lane)
+{
+    if constexpr (Op::kQT == 16) {
+        const int g = lane >> 4;
+        return (2 * s + (g >> 1)) * 64 + 16 * u + (lane & 15) + 32 * (g & 1);
+    } else {
+        return (s * Op::kAU + u) * 64 + lane;
+    }
+}
+
+template <int FMT, bool NBN>
+struct OpI8Q : OpI8T<4, FMT, NBN> {
+    using Base = OpI8T<4, FMT, NBN>;
+    static constexpr int kSteps = 2;         // K = 64 per step
+    static constexpr int kAU = 2;            // one uint4 per row block
+    static constexpr int kBU = 1;
+    static constexpr int kQT = 16;
+    static constexpr int kGroups = 4;
+    static constexpr int kAccN = 8;
+    static constexpr int kRowStride = 16;
+    static constexpr int kMfma = 2;
+    using acc_t = i32x8;
+    using seed_t = f32x8;
+    static __device__ __forceinline__ int gate_min(const i32x8 &acc) { return min8(acc); }
+    static __device__ __forceinline__ int group_min(const i32x8 &a, int g)
+    {
+        return min(min(min(a[4 * g], a[4 * g + 1]), a[4 * g + 2]), a[4 * g + 3]);
+    }
+    static __device__ __forceinline__ float key(const i32x8 &acc, int r, uint32_t parity, int h)
+    {
+        const int d = acc[r];
+        const int row = 16 * (r >> 2) + 4 * h + (r & 3);
+        return d >= (1 << 29) ? __builtin_inff() : (float)(2 * d + (int)((parity >> row) & 1u));
+    }
+    static __device__ __forceinline__ void load_b(const void *q, const int32_t *, int64_t qi, bool ok, int h,
+                                                  uint4 (&b)[kSteps][kBU], int &sb)
+    {
+        const uint4 *qrow = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(q) + (ok ? qi : 0) * kDim);
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s) {
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (ok) v = qrow[4 * s + h];
+            const uint32_t m = 0x7f7f7f7fu;
+            b[s][0] = ok ? make_uint4(v.x ^ m, v.y ^ m, v.z ^ m, v.w ^ m) : make_uint4(0u, 0u, 0u, 0u);
+        }
+        sb = 127;
+    }
+    static __device__ __forceinline__ i32x8 mma(const uint4 (&a)[kAU], const uint4 (&b)[kBU], i32x8 c, int, int)
+    {
+        const i32x4v bv = __builtin_bit_cast(i32x4v, b[0]);
+        const i32x4v lo = __builtin_amdgcn_mfma_i32_16x16x64_i8(__builtin_bit_cast(i32x4v, a[0]), bv,
+                                                                __builtin_shufflevector(c, c, 0, 1, 2, 3), 0, 0, 0);
+        const i32x4v hi = __builtin_amdgcn_mfma_i32_16x16x64_i8(__builtin_bit_cast(i32x4v, a[1]), bv,
+                                                                __builtin_shufflevector(c, c, 4, 5, 6, 7), 0, 0, 0);
+        return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+    }
+};
+
+template <class Base16, bool BF>
+struct OpH16Q : Base16 {
+    static constexpr int kSteps = 4;         // K = 32 per step
+    static constexpr int kAU = 2;
+    static constexpr int kBU = 1;
+    static constexpr int kQT = 16;
+    static constexpr int kGroups = 4;
+    static constexpr int kAccN = 8;
+    static constexpr int kRowStride = 16;
+    static constexpr int kMfma = 2;
+    using acc_t = f32x8;
+    using seed_t = f32x8;
+    static __device__ __forceinline__ float gate_min(const f32x8 &acc) { return min8(acc); }
+    static __device__ __forceinline__ float group_min(const f32x8 &a, int g)
+    {
+        return __builtin_fminf(__builtin_fminf(__builtin_fminf(a[4 * g], a[4 * g + 1]), a[4 * g + 2]), a[4 * g + 3]);
+    }
+    static __device__ __forceinline__ float key(const f32x8 &acc, int r, uint32_t, int) { return acc[r]; }
+    static __device__ __forceinline__ void load_b(const void *q, const int32_t *, int64_t qi, bool ok, int h,
+                                                  uint4 (&b)[kSteps][kBU], int &sb)
+    {
+        const uint8_t *qrow = static_cast<const uint8_t *>(q) + (ok ? qi : 0) * kDim + 8 * h;
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s) {
+            uint2 raw = make_uint2(0u, 0u);
+            if (ok) raw = *reinterpret_cast<const uint2 *>(qrow + 32 * s);
+            b[s][0] = Base16::cvt8(raw, -2.0f);
+        }
+        sb = 127;
+    }
+    static __device__ __forceinline__ f32x8 mma(const uint4 (&a)[kAU], const uint4 (&b)[kBU], f32x8 c, int, int)
+    {
+        f32x4v lo, hi;
+        if constexpr (BF) {
+            const bf16x8 bv = __builtin_bit_cast(bf16x8, b[0]);
+            lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[0]), bv,
+                                                         __builtin_shufflevector(c, c, 0, 1, 2, 3), 0, 0, 0);
+            hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[1]), bv,
+                                                         __builtin_shufflevector(c, c, 4, 5, 6, 7), 0, 0, 0);
+        } else {
+            const f16x8 bv = __builtin_bit_cast(f16x8, b[0]);
+            lo = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a[0]), bv,
+                                                        __builtin_shufflevector(c, c, 0, 1, 2, 3), 0, 0, 0);
+            hi = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a[1]), bv,
+                                                        __builtin_shufflevector(c, c, 4, 5, 6, 7), 0, 0, 0);
+        }
+        return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+    }
+};
+
+// The 16x16 form of each operand policy that has one (void: none).
+template <class Op> struct Square16 { using type = void; };
+template <> struct Square16<OpI8> { using type = OpI8Q<FMT_I8, false>; };
+template <> struct Square16<OpI8N> { using type = OpI8Q<FMT_I8N, true>; };
+template <> struct Square16<OpF16> { using type = OpH16Q<OpF16, false>; };
+template <> struct Square16<OpBF16> { using type = OpH16Q<OpBF16, true>; };
+
 // ---------------------------------------------------------------------------
 // K1: distances + top-(k+1).
 //
-// Work item = (query block of W * 32 * NT queries, reference slice).
-// Each wave keeps 32*NT queries' operand fragments in registers; the
+// Work item = (query block of W * kQT * NT queries, reference slice).
+// Each wave keeps kQT*NT queries' operand fragments in registers; the
 // workgroup streams 32-row reference tiles through NB LDS stages of MT
 // tiles.  With references as the MFMA M dimension and queries as N, lane l's
-// 16 accumulator registers are 16 references of one query (column l & 31):
-// register r is row 8*(r/4) + 4*(l/32) + r%4.
+// accumulator registers are references of one query: in the 32x32 shape 16
+// registers, column l & 31, register r being row 8*(r/4) + 4*(l/32) + r%4;
+// in the 16x16 shape 8 registers, column l & 15, row 16*(r/4) + 4*(l/16) + r%4.
 //
 // Selection.  Each lane keeps a sorted register list of the KP best
-// (d', index) pairs of its query among the rows it has seen (lanes l and
-// l+32 each see half of every tile and keep separate lists).  A tile is
-// gated by the minimum of the lane's 16 values: only when some lane of the
-// wave beats its current KP-th value does the wave walk the 16 registers and
-// insert.  Rows reach a lane in increasing index order, so "strictly less
+// (d', index) pairs of its query among the rows it has seen (the kGroups
+// lanes of a query each see their share of every tile and keep separate
+// lists).  A tile is gated by the minimum of the lane's values: only when
+// some lane of the wave beats its current KP-th value does the wave walk the
+// registers and insert.  Rows reach a lane in increasing index order, so "strictly less
 // than" on d' alone realises the (distance, index) order.
 //
 // Original NBNN (Op::kNbnn, Algorithm 1).  The index holds the references
@@ -335,10 +493,10 @@ static __device__ __forceinline__ void tile_insert(const typename Op::acc_t &acc
     // this (rarely taken) path instead of being hoisted into the gate
     int base = row0;
     asm volatile("" : "+v"(base));
-    // registers 4g..4g+3 hold rows 8g + 4h + 0..3: only the groups whose
-    // minimum passes the gate are walked (usually one)
+    // registers 4g..4g+3 hold rows kRowStride*g + 4h + 0..3: only the groups
+    // whose minimum passes the gate are walked (usually one)
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
+    for (int g = 0; g < Op::kAccN / 4; ++g) {
         if (__builtin_amdgcn_ballot_w64(Op::group_min(acc, g) < gt) == 0) continue;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -346,7 +504,7 @@ static __device__ __forceinline__ void tile_insert(const typename Op::acc_t &acc
             const float v = Op::key(acc, r, pm, h);
             const bool take = v < thr;
             if (__builtin_amdgcn_ballot_w64(take) != 0) {
-                if (take) list_insert<KP>(v, base + 8 * g + i, ld, li, thr);
+                if (take) list_insert<KP>(v, base + Op::kRowStride * g + i, ld, li, thr);
             }
         }
     }
@@ -448,14 +606,47 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // order each read after the copy it needs.
 template <class Op>
 static __device__ __forceinline__ void tile_reads(const uint4 *frag, const float4 *seed, const int32_t *rsc,
-                                                  int lane, int h, uint4 (&av)[Op::kSteps][Op::kAU], f32x16 &sd,
-                                                  int &sa)
+                                                  int lane, int h, uint4 (&av)[Op::kSteps][Op::kAU],
+                                                  typename Op::seed_t &sd, int &sa)
 {
-    const uint32_t fa = lds_addr(frag + lane);
+    const uint32_t fa = lds_addr(frag + frag_off<Op>(0, 0, lane));
     const uint32_t ea = lds_addr(seed + h);
     u32x4 a0, a1, a2, a3, a4, a5, a6, a7;
     f32x4 s0, s1, s2, s3;
-    if constexpr (Op::kSteps * Op::kAU == 8) {
+    if constexpr (Op::kQT == 16) {
+        // 16-bit formats, 16x16 blocks: K step s, row block u at byte
+        // offset 2048 s + 256 u from the lane's base; the lane's two seed
+        // groups are 64 bytes apart
+        static_assert(Op::kSteps == 4 && Op::kAU == 2 && !Op::kScaled, "16x16 16-bit layout");
+        asm volatile(
+            "ds_read_b128 %0, %10\n\t"
+            "ds_read_b128 %1, %10 offset:256\n\t"
+            "ds_read_b128 %2, %10 offset:2048\n\t"
+            "ds_read_b128 %3, %10 offset:2304\n\t"
+            "ds_read_b128 %4, %10 offset:4096\n\t"
+            "ds_read_b128 %5, %10 offset:4352\n\t"
+            "ds_read_b128 %6, %10 offset:6144\n\t"
+            "ds_read_b128 %7, %10 offset:6400\n\t"
+            "ds_read_b128 %8, %11\n\t"
+            "ds_read_b128 %9, %11 offset:64\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(a0), "=&v"(a1), "=&v"(a2), "=&v"(a3), "=&v"(a4), "=&v"(a5), "=&v"(a6), "=&v"(a7),
+              "=&v"(s0), "=&v"(s1)
+            : "v"(fa), "v"(ea)
+            : "memory");
+        const u32x4 a[8] = {a0, a1, a2, a3, a4, a5, a6, a7};
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) av[s][u] = __builtin_bit_cast(uint4, a[2 * s + u]);
+        sa = 127;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            sd[j] = s0[j];
+            sd[4 + j] = s1[j];
+        }
+        return;
+    } else if constexpr (Op::kSteps * Op::kAU == 8) {
         static_assert(!Op::kScaled, "unscaled formats only");
         asm volatile(
             "ds_read_b128 %0, %12\n\t"
@@ -522,11 +713,13 @@ static __device__ __forceinline__ void tile_reads(const uint4 *frag, const float
         av[1][1] = __builtin_bit_cast(uint4, a3);
         sa = r;
     }
-    const f32x4 sv[4] = {s0, s1, s2, s3};
+    if constexpr (Op::kQT == 32) {
+        const f32x4 sv[4] = {s0, s1, s2, s3};
 #pragma unroll
-    for (int g = 0; g < 4; ++g)
+        for (int g = 0; g < 4; ++g)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) sd[4 * g + j] = sv[g][j];
+            for (int j = 0; j < 4; ++j) sd[4 * g + j] = sv[g][j];
+    }
 }
 
 // One pipeline step: the MFMA chain of a new tile (into acc_new) and the
@@ -536,7 +729,7 @@ static __device__ __forceinline__ void tile_reads(const uint4 *frag, const float
 template <class Op, int KP, int NT>
 static __device__ __forceinline__ void pipe_step(typename Op::acc_t (&acc_new)[NT],
                                                  const typename Op::acc_t (&acc_old)[NT],
-                                                 const uint4 (&bq)[NT][Op::kSteps][Op::kAU], const int (&sb)[NT],
+                                                 const uint4 (&bq)[NT][Op::kSteps][Op::kBU], const int (&sb)[NT],
                                                  const uint4 *frag, const float4 *seed, const int32_t *rsc, int lane,
                                                  int h, float (&thr)[NT], typename Op::gate_t (&gt)[NT], float (&ld)[NT][KP],
                                                  int (&li)[NT][KP], int row_old, const uint32_t *parity)
@@ -544,7 +737,7 @@ static __device__ __forceinline__ void pipe_step(typename Op::acc_t (&acc_new)[N
     using acc_t = typename Op::acc_t;
     constexpr int S = Op::kSteps;
     constexpr int AU = Op::kAU;
-    f32x16 sd;
+    typename Op::seed_t sd;
     int sa;
     uint4 av[S][AU];
     tile_reads<Op>(frag, seed, rsc, lane, h, av, sd, sa);
@@ -559,7 +752,7 @@ static __device__ __forceinline__ void pipe_step(typename Op::acc_t (&acc_new)[N
             acc_new[nt] = Op::mma(av[s], bq[nt][s], s == 0 ? seed_acc : acc_new[nt], sa, sb[nt]);
     }
 #pragma unroll
-    for (int i = 0; i < S * NT; ++i) {
+    for (int i = 0; i < S * NT * Op::kMfma; ++i) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);     // one MFMA
         __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);     // up to two vector ops
     }
@@ -595,7 +788,7 @@ static __device__ __forceinline__ void static_for(F &&f)
 template <class Op>
 struct TileRegs {
     uint4 av[Op::kSteps][Op::kAU];
-    f32x16 sd;
+    typename Op::seed_t sd;
     int sa;
 };
 
@@ -610,10 +803,10 @@ static __device__ __forceinline__ void tile_load(const uint4 *frag, const float4
 #pragma unroll
     for (int s = 0; s < Op::kSteps; ++s)
 #pragma unroll
-        for (int u = 0; u < Op::kAU; ++u) t.av[s][u] = frag[(s * Op::kAU + u) * 64 + lane];
+        for (int u = 0; u < Op::kAU; ++u) t.av[s][u] = frag[frag_off<Op>(s, u, lane)];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        const float4 sv = seed[2 * g + h];
+    for (int g = 0; g < Op::kAccN / 4; ++g) {
+        const float4 sv = seed[(Op::kRowStride / 4) * g + h];
         t.sd[4 * g + 0] = sv.x;
         t.sd[4 * g + 1] = sv.y;
         t.sd[4 * g + 2] = sv.z;
@@ -628,7 +821,7 @@ static __device__ __forceinline__ void tile_load(const uint4 *frag, const float4
 template <class Op, int KP, int NT>
 static __device__ __forceinline__ void pipe_step_regs(typename Op::acc_t (&acc_new)[NT],
                                                       const typename Op::acc_t (&acc_old)[NT],
-                                                      const uint4 (&bq)[NT][Op::kSteps][Op::kAU],
+                                                      const uint4 (&bq)[NT][Op::kSteps][Op::kBU],
                                                       const int (&sb)[NT], const TileRegs<Op> &cur, int h,
                                                       float (&thr)[NT], typename Op::gate_t (&gt)[NT], float (&ld)[NT][KP],
                                                       int (&li)[NT][KP], int row_old, const uint32_t *parity)
@@ -648,8 +841,9 @@ static __device__ __forceinline__ void pipe_step_regs(typename Op::acc_t (&acc_n
     // The gate reads the previous tile's accumulators, whose last MFMAs were
     // issued just before this block: LEAD MFMAs go first so that those
     // chains have completed when the gate's first vector op issues.
-    constexpr int LEAD = LNBNN_GATE_LEAD < S * NT ? LNBNN_GATE_LEAD : S * NT;
-    constexpr int NREAD = S * Op::kAU + 4 + (Op::kScaled ? 1 : 0);   // next tile's LDS loads
+    constexpr int NM = S * NT * Op::kMfma;        // MFMAs of the step
+    constexpr int LEAD = LNBNN_GATE_LEAD < NM ? LNBNN_GATE_LEAD : NM;
+    constexpr int NREAD = S * Op::kAU + Op::kAccN / 4 + (Op::kScaled ? 1 : 0);   // next tile's LDS loads
 #if LNBNN_READS_AFTER_LEAD
     __builtin_amdgcn_sched_group_barrier(0x008, LEAD, 0);
     __builtin_amdgcn_sched_group_barrier(0x100, NREAD, 0);
@@ -658,7 +852,7 @@ static __device__ __forceinline__ void pipe_step_regs(typename Op::acc_t (&acc_n
     __builtin_amdgcn_sched_group_barrier(0x008, LEAD, 0);
 #endif
 #pragma unroll
-    for (int i = LEAD; i < S * NT; ++i) {
+    for (int i = LEAD; i < NM; ++i) {
         __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);     // up to three vector ops
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);     // one MFMA
     }
@@ -682,7 +876,7 @@ void k_dist_topk(DistArgs a)
     constexpr int AU = Op::kAU;
     constexpr int TILE_U4 = S * AU * 64;          // uint4 per 32-row tile
     constexpr int STAGE_U4 = MT * TILE_U4;
-    constexpr int QW = 32 * NT;                   // queries per wave
+    constexpr int QW = Op::kQT * NT;              // queries per wave
     constexpr int QB = W * QW;                    // queries per workgroup
     constexpr int PD = NB - 1;                    // stages in flight ahead of the one computed
     constexpr int LPS = StageLoads<Op, MT, W>::total;   // loads per wave per stage
@@ -727,7 +921,7 @@ void k_dist_topk(DistArgs a)
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int h = lane >> 5, col = lane & 31;
+    const int h = lane / Op::kQT, col = lane & (Op::kQT - 1);   // lane group, query column
     const int64_t n_q = a.bd->n_q;
     const void *q_src = a.q ? a.q : a.bd->q;
     const int64_t n_qb = (n_q + QB - 1) / QB;
@@ -751,12 +945,12 @@ void k_dist_topk(DistArgs a)
             const int64_t t1 = min(t0 + (int64_t)a.chunk_tiles, ts1);
             const int n_t = (int)(t1 - t0);           // multiple of 8, so of MT
 
-            uint4 bq[NT][S][AU];
+            uint4 bq[NT][S][Op::kBU];
             int sb[NT];
             int64_t qi[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
-                qi[nt] = qb * QB + wave * QW + nt * 32 + col;
+                qi[nt] = qb * QB + wave * QW + nt * Op::kQT + col;
                 Op::load_b(q_src, a.q_scale, qi[nt], qi[nt] < n_q, h, bq[nt], sb[nt]);
             }
 
@@ -766,7 +960,7 @@ void k_dist_topk(DistArgs a)
             typename Op::gate_t gt[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
-                const int64_t base = ((int64_t)(slice * 2 + h) * a.q_cap + qi[nt]) * KP;
+                const int64_t base = ((int64_t)(slice * Op::kGroups + h) * a.q_cap + qi[nt]) * KP;
                 const bool load = !Op::kNbnn && c > 0 && qi[nt] < n_q;
 #pragma unroll
                 for (int p = 0; p < KP; ++p) {
@@ -846,7 +1040,7 @@ void k_dist_topk(DistArgs a)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) acc1[nt][r] = Op::init();
+                for (int r = 0; r < Op::kAccN; ++r) acc1[nt][r] = Op::init();
             int row_prev = 0;
             int buf = 0;
             if constexpr (kCounters) {
@@ -1013,7 +1207,7 @@ void k_dist_topk(DistArgs a)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 if (qi[nt] < n_q) {
-                    const int64_t base = ((int64_t)(slice * 2 + h) * a.q_cap + qi[nt]) * KP;
+                    const int64_t base = ((int64_t)(slice * Op::kGroups + h) * a.q_cap + qi[nt]) * KP;
 #pragma unroll
                     for (int p = 0; p < KP; ++p) {
                         a.part_d[base + p] = ld[nt][p];
@@ -1054,6 +1248,18 @@ static void *pick_variant(int v)
         // 8-tile stages for one query tile per wave (the longer lists): 4 KB tiles
         if constexpr (KP <= 40 && Op::kSteps * Op::kAU == 4)
             if (v == 11) return kernel_ptr<Op, KP, 1, 8, 8, 3>();
+        // 16x16 output blocks, in the formats that have that form: four
+        // lists per query, so shorter ones
+        using Q16 = typename Square16<Op>::type;
+        if constexpr (!std::is_void<Q16>::value && KP <= 16) {
+            if constexpr (Op::kSteps * Op::kAU == 4) {      // 4 KB tiles
+                if (v == 13) return kernel_ptr<Q16, KP, 2, 8, 8, 4>();
+                if constexpr (KP <= 6)
+                    if (v == 15) return kernel_ptr<Q16, KP, 4, 8, 8, 4>();
+            } else {
+                if (v == 14) return kernel_ptr<Q16, KP, 2, 4, 8, 4>();
+            }
+        }
         // two query tiles of long lists, one wave per SIMD: FP8 candidate lists
         if constexpr (Op::kFmt == FMT_FP8 && KP > 20)
             if (v == 12) return kernel_ptr<Op, KP, 2, 8, 4, 3>();

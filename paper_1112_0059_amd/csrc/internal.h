@@ -33,14 +33,17 @@ struct BatchDesc {
     float *nbr_dist;    // [n_q, k+1] squared distances, or null
 };
 
-// A distance-kernel variant: queries per wave = 32 * nt, reference tiles
-// per LDS stage = mt, waves per workgroup.  The list length the kernel keeps
-// (>= k + 1) is a separate compile-time parameter.
+// A distance-kernel variant: queries per wave = qt * nt, reference tiles
+// per LDS stage = mt, waves per workgroup.  qt is the MFMA output block's
+// query width (32: 32x32 blocks, two lists per query; 16: 16x16 blocks, four
+// lists per query).  The list length the kernel keeps (>= k + 1) is a
+// separate compile-time parameter.
 struct Variant {
     int nt;
     int mt;
     int waves;
     int buffers;    // LDS stages: the kernel keeps buffers - 1 stages in flight
+    int qt;
 };
 
 struct DistArgs {
@@ -56,7 +59,7 @@ struct DistArgs {
     int32_t n_slices;
     int32_t chunk_tiles;        // tiles one item runs before the workgroup moves on (multiple of 8)
     int64_t q_cap;              // capacity: part buffers are laid out for q_cap queries
-    float *part_d;              // [n_slices * 2][q_cap][kp]
+    float *part_d;              // [n_slices * lists per query][q_cap][kp]
     int32_t *part_i;
     int32_t *status;            // bit 0: a bounded stage wait gave up (set by the kernels that
                                 // read the lists, which carry the mark as a NaN key)
@@ -85,7 +88,7 @@ struct RerankArgs {
     const float *ref_f32;       // f32 references [n_refs, 128]
     const int32_t *labels;
     int64_t n_refs;
-    int32_t n_lists;            // 2 * n_slices
+    int32_t n_lists;            // n_slices * lists per query (at most 64)
     int32_t kp_stride;          // list length in the part buffers
     int32_t n_cand;             // candidates kept per query (4k)
     int32_t k;
@@ -108,7 +111,7 @@ struct FinishArgs {
     const int64_t *offsets;     // device [n_img + 1]
     const int32_t *labels;      // [n_refs]
     int64_t n_refs;
-    int32_t n_lists;            // 2 * n_slices
+    int32_t n_lists;            // n_slices * lists per query (at most 64)
     int32_t kp_stride;          // list length in the part buffers
     int32_t k;
     int32_t n_classes;

@@ -105,7 +105,7 @@ __global__ void k_seed_u8(const uint8_t *__restrict__ refs, int64_t n_refs, int6
 }
 
 // ---------------------------------------------------------------------------
-// K2: finish.  One thread per query: merge the 2*n_slices sorted partial
+// K2: finish.  One thread per query: merge the n_lists sorted partial
 // lists into the k+1 best (d', index) pairs, then apply Algorithm 2's update:
 // dist_B is the (k+1)-th distance, and each class met among the first k
 // neighbours, at its first (= nearest) occurrence, adds dist_C - dist_B to
@@ -298,25 +298,29 @@ __global__ void k_fill_u64(unsigned long long *p, const BatchDesc *bd, int32_t n
 // Variant table and dispatch
 // ---------------------------------------------------------------------------
 static const Variant kVariants[] = {
-    // nt, mt, waves, buffers
-    {1, 2, 4, 4},   // 0
-    {2, 2, 4, 4},   // 1
-    {2, 4, 4, 2},   // 2
-    {2, 2, 4, 2},   // 3
-    {2, 4, 8, 4},   // 4
-    {2, 2, 8, 8},   // 5
-    {1, 4, 8, 4},   // 6
-    {2, 4, 4, 3},   // 7
-    {2, 8, 8, 4},   // 8  (4 KB tiles only: INT8, FP8)
-    {2, 4, 8, 8},   // 9  (4 KB tiles only: INT8, FP8)
-    {2, 8, 8, 3},   // 10 (160-element INT8 rows only)
-    {1, 8, 8, 3},   // 11 (8-bit formats: INT8 rows of 128 or 160, FP8 lists up to 40)
-    {2, 8, 4, 3},   // 12 (FP8 lists of 40 and 64: one wave per SIMD)
+    // nt, mt, waves, buffers, qt
+    {1, 2, 4, 4, 32},   // 0
+    {2, 2, 4, 4, 32},   // 1
+    {2, 4, 4, 2, 32},   // 2
+    {2, 2, 4, 2, 32},   // 3
+    {2, 4, 8, 4, 32},   // 4
+    {2, 2, 8, 8, 32},   // 5
+    {1, 4, 8, 4, 32},   // 6
+    {2, 4, 4, 3, 32},   // 7
+    {2, 8, 8, 4, 32},   // 8  (4 KB tiles only: INT8, FP8)
+    {2, 4, 8, 8, 32},   // 9  (4 KB tiles only: INT8, FP8)
+    {2, 8, 8, 3, 32},   // 10 (160-element INT8 rows only)
+    {1, 8, 8, 3, 32},   // 11 (8-bit formats: INT8 rows of 128 or 160, FP8 lists up to 40)
+    {2, 8, 4, 3, 32},   // 12 (FP8 lists of 40 and 64: one wave per SIMD)
+    {2, 8, 8, 4, 16},   // 13 (16x16 blocks, INT8 rows of 128)
+    {2, 4, 8, 4, 16},   // 14 (16x16 blocks, FP16 / BF16)
+    {4, 8, 8, 4, 16},   // 15 (16x16 blocks, INT8 rows of 128, lists up to 6)
 };
 static const char *kVariantNames[] = {"w4_nt1_mt2_nb4", "w4_nt2_mt2_nb4", "w4_nt2_mt4_nb2", "w4_nt2_mt2_nb2",
                                       "w8_nt2_mt4_nb4", "w8_nt2_mt2_nb8", "w8_nt1_mt4_nb4", "w4_nt2_mt4_nb3",
                                       "w8_nt2_mt8_nb4", "w8_nt2_mt4_nb8", "w8_nt2_mt8_nb3", "w8_nt1_mt8_nb3",
-                                      "w4_nt2_mt8_nb3"};
+                                      "w4_nt2_mt8_nb3", "q16_w8_nt2_mt8_nb4", "q16_w8_nt2_mt4_nb4",
+                                      "q16_w8_nt4_mt8_nb4"};
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int num_variants() { return kNumVariants; }
@@ -347,6 +351,10 @@ bool variant_supports(int v, int fmt, int kp)
     // in these stage shapes
     if (fmt == FMT_I8L) return v == 11 || ((v == 2 || v == 7 || v == 10) && b <= 16);
     if (v == 10) return false;
+    // 16x16 output blocks: INT8 (128-element rows) and the 16-bit formats
+    if (v == 13) return (fmt == FMT_I8 || fmt == FMT_I8N) && b <= 16;
+    if (v == 14) return (fmt == FMT_F16 || fmt == FMT_BF16) && b <= 16;
+    if (v == 15) return (fmt == FMT_I8 || fmt == FMT_I8N) && b <= 6;
     if (v == 12) return fmt == FMT_FP8 && b > 20;
     // one query tile per wave with 8-tile stages: the 4 KB-tile formats
     if (v == 11) return fmt == FMT_I8 || fmt == FMT_I8N || (fmt == FMT_FP8 && b <= 40);

@@ -131,7 +131,7 @@ static __device__ __forceinline__ bool pair_less(float d0, int i0, float d1, int
 }
 
 // One thread per query: the n_cand best (key, index) pairs over the
-// 2 * n_slices sorted candidate lists of kp_stride entries each (together at
+// n_lists sorted candidate lists of kp_stride entries each (together at
 // least n_cand; entries past a list's real rows carry +inf keys and lose).
 __global__ __launch_bounds__(256) void k_cand_merge(RerankArgs a)
 {

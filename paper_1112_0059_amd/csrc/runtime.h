@@ -71,6 +71,7 @@ struct Plan {
     int fmt = 0;
     int kpb = 0;                // compiled list length
     int n_slices = 1;
+    int n_lists = 2;            // partial lists per query: n_slices * lists per slice
     int tiles_per_slice = 0;
     int grid = 1;
     int chunk_tiles = 8;        // tiles per chunk of the chunk-major walk

@@ -1,0 +1,67 @@
+"""The project autotuner's search (lnbnn_autotune with an empty cache): it
+times the variants that can serve the call, pins the fastest setting, writes
+it to the cache, and a second call reads it back without timing; the pinned
+setting classifies exactly like the oracle."""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1112_0059_amd as L
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("mode", [L.LNBNN_EXACT_I8, L.LNBNN_EXACT_F16, L.LNBNN_NBNN_I8])
+def test_autotune_search_pins_and_caches(tmp_path, mode):
+    import torch
+    cfg = synth.scaled(synth.CONFIGS["M"], n_classes=20, n_img=24, q_lo=300, q_hi=900,
+                       index_seed=8100, query_seed=8200)      # 450k references
+    R, labels = synth.gen_index(cfg)
+    Q, off, _ = synth.gen_queries(cfg)
+    ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(mode))
+    cache = str(tmp_path / "cache.json")
+    try:
+        dq = torch.from_numpy(Q).cuda()
+        t0 = time.perf_counter()
+        v = L.lnbnn_autotune(ix, dq, off, 10, mode, cache_path=cache)
+        t_search = time.perf_counter() - t0
+        _say(f"mode {mode}: search picked {L.lnbnn_variant_name(v)} in {t_search:.1f} s")
+        with open(cache) as f:
+            entries = json.load(f)
+        assert len(entries) == 1
+        (key, val), = entries.items()
+        assert f"n_refs={cfg.n_refs}" in key and key.endswith(f"mode={mode}") and (val & 0xff) == v
+        assert (val >> 8) in (0, 2048, 4096, 8192)
+        # the pinned setting classifies exactly
+        cls, tot, _, _ = L.lnbnn_classify(ix, Q, off, 10, mode, flags=L.LNBNN_TIMING)
+        assert L.lnbnn_last_timing(ix)["tile_variant"] == v
+        if mode == L.LNBNN_NBNN_I8:
+            _, _, D = oracle.knn_class_block(Q, R, labels, cfg.n_classes, 1)
+            wt, wc = oracle.nbnn(D, off)
+        else:
+            wt, wc, _, _ = oracle.classify(Q, R, labels, cfg.n_classes, off, 10, route="block")
+        assert np.array_equal(tot, wt) and np.array_equal(cls, wc)
+        # a fresh index of the same shape reads the choice back without timing
+        ix2 = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(mode))
+        try:
+            t0 = time.perf_counter()
+            v2 = L.lnbnn_autotune(ix2, dq, off, 10, mode, cache_path=cache)
+            t_hit = time.perf_counter() - t0
+            _say(f"cache hit in {t_hit * 1e3:.1f} ms")
+            assert v2 == v and t_hit < t_search / 5
+        finally:
+            ix2.free()
+    finally:
+        ix.free()

@@ -103,6 +103,37 @@ def test_tiny_chunked_walk(tiny, variant, mode):
         L.lnbnn_set_tuning(ix, mode, 10)
 
 
+@pytest.mark.parametrize("mode", MODES)
+def test_tiny_16x16_blocks(tiny, mode):
+    """The variants built on 16x16 MFMA blocks (four lanes, so four lists,
+    per query): every list length each is built for, with the default split
+    of the reference set (up to 64 partial lists per query to merge) and
+    with few workgroups walking 8-tile chunks (lists parked between chunks)."""
+    cfg, R, labels, Q, off, ix, ref = tiny
+    shapes = [14] if mode != L.LNBNN_EXACT_I8 else [13, 15]
+    assert all(L.lnbnn_variant_name(v).startswith("q16_") for v in shapes)
+    ran = 0
+    for v in shapes:
+        for k in (1, 5, 10):
+            try:
+                L.lnbnn_set_tuning(ix, mode, k, variant=v)
+            except L.LnbnnError:
+                assert v == 15 and k == 10          # 64 queries per wave: lists up to 6
+                continue
+            try:
+                for chunk, wg in ((0, 0), (8, 3)):
+                    _say(f"16x16 variant {v} mode={mode} k={k} chunk={chunk} workgroups={wg}")
+                    L.lnbnn_set_tuning(ix, mode, k, variant=v, chunk_tiles=chunk, max_workgroups=wg)
+                    got = L.lnbnn_classify(ix, Q, off, k, mode, want_neighbours=True, flags=L.LNBNN_TIMING)
+                    t = L.lnbnn_last_timing(ix)
+                    assert t["tile_variant"] == v and (chunk or t["slices"] > 1)
+                    _check_exact(got, ref[k], k)
+                    ran += 1
+            finally:
+                L.lnbnn_set_tuning(ix, mode, k)
+    assert ran >= 6
+
+
 @pytest.mark.parametrize("mode", FORMS)
 def test_device_pointers_and_graph_replays(tiny, mode):
     """Device tensors on torch's stream; the captured graph is replayed with
