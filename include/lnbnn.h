@@ -32,6 +32,20 @@
  *     caller-allocated;
  *   - an index is immutable after it is built and may be shared by
  *     lnbnn_classify callers and the serving loop.
+ *
+ * Environment (read when the named call runs):
+ *   LNBNN_HBM_BUDGET   serving budget in bytes (suffix K, M or G allowed) for
+ *                      lnbnn_build_index calls that pass hbm_budget_bytes = 0
+ *                      (otherwise a quarter of the free device memory);
+ *   LNBNN_TUNE_CACHE   tuning cache file lnbnn_autotune reads and writes when
+ *                      its cache_path is NULL;
+ *   LNBNN_LOG          1: one line per index build, graph capture, tuner
+ *                      decision and serving start on stderr, prefixed
+ *                      "[lnbnn]"; unset or 0: silent;
+ *   LNBNN_WAIT_SPINS   bound of the distance kernel's stage waits (see
+ *                      lnbnn_classify);
+ *   LNBNN_FAULT        alloc | launch: the named step fails with an error
+ *                      (to exercise error paths; never set in production).
  */
 #ifndef LNBNN_H
 #define LNBNN_H
@@ -308,6 +322,34 @@ int lnbnn_poll(lnbnn_index *ix, uint64_t ticket, int32_t *out_class,
 /* Serving parameters (before the first submit, else EBUSY): maximum
  * descriptors per batch and batches in flight (1..4); 0 keeps a default. */
 int lnbnn_serve_config(lnbnn_index *ix, int64_t max_batch_desc, int32_t max_inflight);
+
+/*
+ * Memory accounting of the serving loop (a snapshot; the loop keeps running).
+ * The slots' device workspaces are allocated once when the loop starts and
+ * their measured size (device_bytes) never exceeds hbm_budget (the index's
+ * budget, lnbnn_build_index): a start that would exceed it fails with ENOMEM.
+ * Each request is admitted into a batch only while the batch's descriptors
+ * stay within batch_desc_cap and its images within max_images, so at most
+ * slots * batch_desc_cap descriptors are on the device at any time.
+ * Before the loop has started only hbm_budget is filled (started = 0).
+ * Errors: EINVAL (NULL argument).
+ */
+typedef struct lnbnn_serve_stats {
+    int64_t hbm_budget;          /* bytes */
+    int64_t device_bytes;        /* bytes held by the slots' workspaces */
+    int64_t batch_desc_cap;      /* descriptors per batch */
+    int64_t queued_requests;
+    int64_t queued_desc;         /* descriptors waiting for a batch */
+    int64_t inflight_desc;       /* descriptors of batches on the device */
+    int64_t peak_batch_desc;     /* largest batch admitted so far */
+    int64_t peak_inflight_desc;  /* most descriptors on the device at once so far */
+    int32_t max_images;          /* images per batch */
+    int32_t slots;               /* batches in flight at most */
+    int32_t inflight_batches;
+    int32_t started;
+} lnbnn_serve_stats;
+
+int lnbnn_serve_info(lnbnn_index *ix, lnbnn_serve_stats *out);
 
 /* Thread-local message of the calling thread's last failure ("" if none). */
 const char *lnbnn_last_error(void);

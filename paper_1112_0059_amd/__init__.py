@@ -53,6 +53,15 @@ class lnbnn_tuning(ctypes.Structure):
                 ("max_workgroups", ctypes.c_int32)]
 
 
+class lnbnn_serve_stats(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("batch_desc_cap", ctypes.c_int64), ("queued_requests", ctypes.c_int64),
+                ("queued_desc", ctypes.c_int64), ("inflight_desc", ctypes.c_int64),
+                ("peak_batch_desc", ctypes.c_int64), ("peak_inflight_desc", ctypes.c_int64),
+                ("max_images", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("inflight_batches", ctypes.c_int32), ("started", ctypes.c_int32)]
+
+
 class lnbnn_req_stats(ctypes.Structure):
     _fields_ = [("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
                 ("t_start_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64),
@@ -102,6 +111,7 @@ def load():
                          ctypes.c_int),
         "lnbnn_poll": ([P, u64, P, P, ctypes.POINTER(lnbnn_req_stats)], ctypes.c_int),
         "lnbnn_serve_config": ([P, i64, i32], ctypes.c_int),
+        "lnbnn_serve_info": ([P, ctypes.POINTER(lnbnn_serve_stats)], ctypes.c_int),
         "lnbnn_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -319,6 +329,12 @@ def lnbnn_variant_name(v: int) -> str:
 
 def lnbnn_serve_config(ix: Index, max_batch_desc: int = 0, max_inflight: int = 0):
     _check(load().lnbnn_serve_config(ix.handle, int(max_batch_desc), int(max_inflight)))
+
+
+def lnbnn_serve_info(ix: Index) -> dict:
+    st = lnbnn_serve_stats()
+    _check(load().lnbnn_serve_info(ix.handle, ctypes.byref(st)))
+    return {name: getattr(st, name) for name, _ in lnbnn_serve_stats._fields_}
 
 
 def lnbnn_submit(ix: Index, queries, k: int, mode: int) -> int:

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -42,6 +43,41 @@ bool fault_injected(const char *site)
 {
     const char *f = getenv("LNBNN_FAULT");
     return f && strcmp(f, site) == 0;
+}
+
+// LNBNN_LOG=1: one line on stderr per notable event.
+bool log_enabled()
+{
+    const char *e = getenv("LNBNN_LOG");
+    return e && *e && strcmp(e, "0") != 0;
+}
+
+void log_line(const char *fmt, ...)
+{
+    if (!log_enabled()) return;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    fprintf(stderr, "[lnbnn] %s\n", buf);
+}
+
+// LNBNN_HBM_BUDGET: bytes, with an optional K / M / G suffix; 0 when unset
+// or malformed.
+static int64_t env_budget()
+{
+    const char *e = getenv("LNBNN_HBM_BUDGET");
+    if (!e || !*e) return 0;
+    char *end = nullptr;
+    const double v = strtod(e, &end);
+    if (end == e || !(v > 0)) return 0;
+    double mul = 1;
+    if (*end == 'K' || *end == 'k') mul = 1024.0;
+    else if (*end == 'M' || *end == 'm') mul = 1024.0 * 1024;
+    else if (*end == 'G' || *end == 'g') mul = 1024.0 * 1024 * 1024;
+    else if (*end) return 0;
+    return (int64_t)(v * mul);
 }
 
 static hipError_t dmalloc(void **p, size_t bytes)
@@ -268,6 +304,15 @@ static int blocks_per_cu(lnbnn_index *ix, int v, int fmt, int kpb)
     return n;
 }
 
+// A variant that can run the mode's format and list length, and keeps the
+// mode's candidate rule: the union-of-halves FP8 rule is defined on one list
+// per row half, so pair-list variants do not serve it.
+static bool variant_serves(int v, int mode, int fmt, int kp)
+{
+    if (!variant_supports(v, fmt, kp)) return false;
+    return !(variant(v).pl && mode == LNBNN_FP8_RERANK_2K);
+}
+
 static int default_variant(int fmt, int kp)
 {
     // 8-bit formats: 8-tile stages (8 waves x 64 queries, or 32 queries per
@@ -295,11 +340,11 @@ int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_varia
     }
     int v = forced_variant >= 0 ? forced_variant : tu.variant;
     if (v < 0) v = default_variant(fmt, kp);
-    if (!variant_supports(v, fmt, kp))
+    if (!variant_serves(v, mode, fmt, kp))
         return set_err(LNBNN_EINVAL, "variant %d cannot serve mode %d with k + 1 = %d", v, mode, kp);
     const Variant var = variant(v);
     const int64_t qb = (int64_t)var.waves * var.qt * var.nt;
-    const int groups = 64 / var.qt;              // lists per query and slice
+    const int groups = var.pl ? 1 : 64 / var.qt;  // lists per query and slice
     const int64_t n_qb = std::max<int64_t>(1, (q_cap + qb - 1) / qb);
     const int64_t n_tiles = ix->rows[fmt] / kTileRows;
     const int bpc = blocks_per_cu(ix, v, fmt, kpb);
@@ -309,7 +354,7 @@ int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_varia
     // every workgroup slot busy; each split costs one more partial list per
     // lane group (the merge takes at most 64 lists per query).
     int64_t want = 1;
-    if (n_qb < 2 * resident) want = std::min<int64_t>(64 / groups, (2 * resident + n_qb - 1) / n_qb);
+    if (n_qb < 2 * resident) want = std::min<int64_t>(kMaxLists / groups, (2 * resident + n_qb - 1) / n_qb);
     int64_t tps = (n_tiles + want - 1) / want;
     tps = std::max<int64_t>(8, (tps + 7) / 8 * 8);
     const int64_t S = (n_tiles + tps - 1) / tps;
@@ -690,7 +735,11 @@ extern "C" int lnbnn_build_index(const void *refs, int dtype, int64_t n_refs, in
     ix->device_bytes = bytes;
     size_t free_b = 0, total_b = 0;
     LN_HIP(hipMemGetInfo(&free_b, &total_b));
-    ix->hbm_budget = hbm_budget_bytes ? hbm_budget_bytes : (int64_t)(free_b / 4);
+    const int64_t env_b = env_budget();
+    ix->hbm_budget = hbm_budget_bytes ? hbm_budget_bytes : env_b ? env_b : (int64_t)(free_b / 4);
+    log_line("index built: %lld references, dim %d, %d classes, modes 0x%x, %lld device bytes, serving budget %lld bytes",
+             (long long)ix->n_refs, ix->dim, ix->n_classes, ix->modes, (long long)ix->device_bytes,
+             (long long)ix->hbm_budget);
     *out = ix.release();
     return LNBNN_OK;
 }
@@ -802,6 +851,9 @@ int lnbnn::launch_graph(std::map<std::string, GraphEntry> &graphs, uint64_t &clo
         e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return hip_err(e, "hipGraphInstantiate");
+        log_line("graph captured: mode %d, k %d, %s, %d slices, chunk %d tiles, grid %d, capacity %lld descriptors / "
+                 "%lld images (%zu cached)", io.mode, io.k, variant_name(p.variant), p.n_slices, p.chunk_tiles, p.grid,
+                 (long long)io.q_cap, (long long)io.img_cap, graphs.size() + 1);
         it = graphs.emplace(key, g).first;
     }
     it->second.last_use = ++clock;
@@ -1056,7 +1108,7 @@ extern "C" int lnbnn_set_tuning(lnbnn_index *ix, int mode, int32_t k, const lnbn
     const int list_len = dist_list_len(mode, k);
     const int kpb = kp_bucket(list_len, fmt);
     if (kpb == 0) return set_err(LNBNN_EINVAL, "k = %d is not supported by mode %d", k, mode);
-    if (t->variant >= 0 && !variant_supports(t->variant, fmt, list_len))
+    if (t->variant >= 0 && !variant_serves(t->variant, mode, fmt, list_len))
         return set_err(LNBNN_EINVAL, "variant %d cannot serve k = %d", t->variant, k);
     std::lock_guard<std::mutex> lock(ix->plan_mu);
     if (t->variant < 0 && t->chunk_tiles == 0 && t->max_workgroups == 0)
@@ -1114,6 +1166,10 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
     int rc = validate_classify(ix, queries_dev, dtype, img_offsets, n_images, k, mode, LNBNN_DEVICE_PTRS, true,
                                nullptr, nullptr);
     if (rc) return rc;
+    if (!cache_path) {
+        const char *e = getenv("LNBNN_TUNE_CACHE");
+        if (e && *e) cache_path = e;
+    }
     const int fmt = index_fmt(ix, mode);
     const int kpb = kp_bucket(dist_list_len(mode, k), fmt);
     char arch[64] = "gfx";
@@ -1129,10 +1185,13 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
         // cache value: variant | chunk_tiles << 8 (chunk 0 = whole slice)
         const int cv = it != m.end() ? it->second & 0xff : -1;
         const int cc = it != m.end() ? it->second >> 8 : 0;
-        if (it != m.end() && variant_supports(cv, fmt, dist_list_len(mode, k)) && cc >= 0 && cc % 8 == 0) {
-            std::lock_guard<std::mutex> lock(ix->plan_mu);
-            ix->pinned[{mode, kpb}] = lnbnn_tuning{cv, cc, 0};
+        if (it != m.end() && variant_serves(cv, mode, fmt, dist_list_len(mode, k)) && cc >= 0 && cc % 8 == 0) {
+            {
+                std::lock_guard<std::mutex> lock(ix->plan_mu);
+                ix->pinned[{mode, kpb}] = lnbnn_tuning{cv, cc, 0};
+            }
             if (best_variant) *best_variant = cv;
+            log_line("tuner: cache hit %s -> %s, chunk %d", key.str().c_str(), variant_name(cv), cc);
             return LNBNN_OK;
         }
     }
@@ -1161,7 +1220,7 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
     std::vector<std::pair<double, int>> by_variant;
     const int list_len = dist_list_len(mode, k);
     for (int v = 0; v < num_variants() && !rc; ++v) {
-        if (!variant_supports(v, fmt, list_len)) continue;
+        if (!variant_serves(v, mode, fmt, list_len)) continue;
         double ms = 0;
         if (!(rc = time_setting(v, 0, &ms))) by_variant.push_back({ms, v});
     }
@@ -1187,6 +1246,8 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
     lnbnn_tuning bt{best, best_chunk, 0};
     lnbnn_set_tuning(ix, mode, k, &bt);
     if (best_variant) *best_variant = best;
+    log_line("tuner: %s -> %s, chunk %d (%.2f ms; %zu variants timed)", key.str().c_str(), variant_name(best),
+             best_chunk, best_ms, by_variant.size());
     if (cache_path) {
         auto m = read_cache(cache_path);
         m[key.str()] = best | (best_chunk << 8);

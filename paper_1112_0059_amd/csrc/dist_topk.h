@@ -107,6 +107,8 @@ struct FloatKeys {
     }
     static __device__ __forceinline__ float gate_thr(float thr) { return thr; }
     static __device__ __forceinline__ float key(const f32x16 &acc, int r, uint32_t, int) { return acc[r]; }
+    // key of one accumulator value of tile row `row` (one list per query)
+    static __device__ __forceinline__ float key_at(float v, int, uint32_t) { return v; }
 };
 
 struct OpF16 : FloatKeys {
@@ -269,6 +271,10 @@ struct OpI8T {
     {
         const int d = acc[r];
         const int row = 8 * (r >> 2) + 4 * h + (r & 3);
+        return d >= (1 << 29) ? __builtin_inff() : (float)(2 * d + (int)((parity >> row) & 1u));
+    }
+    static __device__ __forceinline__ float key_at(int d, int row, uint32_t parity)
+    {
         return d >= (1 << 29) ? __builtin_inff() : (float)(2 * d + (int)((parity >> row) & 1u));
     }
     static __device__ __forceinline__ void load_b(const void *q, const int32_t *, int64_t qi, bool ok, int h,
@@ -511,19 +517,125 @@ static __device__ __forceinline__ void tile_insert(const typename Op::acc_t &acc
     gt = Op::gate_thr(thr);
 }
 
+static __device__ __forceinline__ float lmin(float a, float b) { return __builtin_fminf(a, b); }
+static __device__ __forceinline__ int lmin(int a, int b) { return min(a, b); }
+
+template <class Op> using AccT = typename Op::acc_t;
+template <class Op, int NT> using AccArr = typename Op::acc_t[NT];
+
+// Lists each lane keeps: one per query tile, or (PL, pair lists) one for the
+// query it owns.
+template <bool PL, int NT>
+constexpr int lists_per_lane() { return PL ? 1 : NT; }
+
+// Pair lists (32x32 blocks, two query tiles).  Lane l owns the list of
+// query (tile h, column l & 31), h = l / 32: one list per query, which sees
+// every row of every tile, instead of one list per row half.  Its values of
+// a tile sit in two lanes (rows 8g + 0..3 in lane l & 31, rows 8g + 4..7 in
+// lane (l & 31) + 32, both in the accumulator of its query tile), so the
+// insertion path first swaps the upper half of tile 0's accumulator with
+// the lower half of tile 1's (v_permlane32_swap, in place: the accumulators
+// are dead after their gate): then every lane holds its own query's rows
+// 8g + i in a0 and 8g + 4 + i in a1.  The gate needs no
+// swap: each lane compares its values of tile nt with the gate threshold of
+// that tile's query (gq[nt]: its own for nt = h, its partner's otherwise).
+template <class Op, int KP>
+static __device__ __forceinline__ void tile_insert_pl(AccT<Op> &a0, AccT<Op> &a1, float &thr,
+                                                      typename Op::gate_t &gt, typename Op::gate_t (&gq)[2],
+                                                      float (&ld)[KP], int (&li)[KP], int row0, int h,
+                                                      const uint32_t *parity)
+{
+    using E = typename Op::gate_t;                 // accumulator element type
+    static_assert(Op::kQT == 32 && Op::kAccN == 16, "pair lists are built on 32x32 blocks");
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const auto p = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(uint32_t, (E)a0[r]),
+                                                        __builtin_bit_cast(uint32_t, (E)a1[r]), false, false);
+        a0[r] = __builtin_bit_cast(E, (uint32_t)p[0]);
+        a1[r] = __builtin_bit_cast(E, (uint32_t)p[1]);
+    }
+    uint32_t pm = 0;
+    if constexpr (Op::kParity) pm = load_uniform(parity, __builtin_amdgcn_readfirstlane(row0 >> 5));
+    int base = row0;                               // opaque, as in tile_insert
+    asm volatile("" : "+v"(base));
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        if (__builtin_amdgcn_ballot_w64(lmin(Op::group_min(a0, g), Op::group_min(a1, g)) < gt) == 0) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float v = Op::key_at(a0[4 * g + i], 8 * g + i, pm);
+            const bool take = v < thr;
+            if (__builtin_amdgcn_ballot_w64(take) != 0) {
+                if (take) list_insert<KP>(v, base + 8 * g + i, ld, li, thr);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float v = Op::key_at(a1[4 * g + i], 8 * g + 4 + i, pm);
+            const bool take = v < thr;
+            if (__builtin_amdgcn_ballot_w64(take) != 0) {
+                if (take) list_insert<KP>(v, base + 8 * g + 4 + i, ld, li, thr);
+            }
+        }
+    }
+    gt = Op::gate_thr(thr);
+    const E other = __shfl_xor(gt, 32);
+    gq[0] = h == 0 ? gt : other;
+    gq[1] = h == 0 ? other : gt;
+}
+
+// Gate of the NT query tiles of one reference tile: does some lane hold a
+// value below its list's gate threshold?  (Pair lists: one answer for both
+// tiles, in any[0].)
+template <class Op, int NT, bool PL>
+static __device__ __forceinline__ void gate_any(const typename Op::acc_t (&acc)[NT],
+                                                const typename Op::gate_t (&gt)[lists_per_lane<PL, NT>()],
+                                                const typename Op::gate_t (&gq)[NT], bool (&any)[NT])
+{
+    if constexpr (PL) {
+        any[0] = __builtin_amdgcn_ballot_w64((Op::gate_min(acc[0]) < gq[0]) | (Op::gate_min(acc[1]) < gq[1])) != 0;
+        any[1] = false;
+    } else {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) any[nt] = __builtin_amdgcn_ballot_w64(Op::gate_min(acc[nt]) < gt[nt]) != 0;
+    }
+}
+
+// Insertions for the tiles whose gate passed (rare).
+template <class Op, int KP, int NT, bool PL>
+static __device__ __forceinline__ void gate_insert(AccArr<Op, NT> &acc, const bool (&any)[NT],
+                                                   float (&thr)[lists_per_lane<PL, NT>()],
+                                                   typename Op::gate_t (&gt)[lists_per_lane<PL, NT>()],
+                                                   typename Op::gate_t (&gq)[NT],
+                                                   float (&ld)[lists_per_lane<PL, NT>()][KP],
+                                                   int (&li)[lists_per_lane<PL, NT>()][KP], int row0, int h,
+                                                   const uint32_t *parity)
+{
+    if constexpr (PL) {
+        if (__builtin_expect(any[0], 0))
+            tile_insert_pl<Op, KP>(acc[0], acc[1], thr[0], gt[0], gq, ld[0], li[0], row0, h, parity);
+    } else {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+            if (__builtin_expect(any[nt], 0))
+                tile_insert<Op, KP>(acc[nt], thr[nt], gt[nt], ld[nt], li[nt], row0, h, parity);
+    }
+}
+
 // Gate + insert for the NT query tiles of one reference tile.  All gates
 // are computed before any branch so they can overlap the next MFMA chain.
-template <class Op, int KP, int NT>
-static __device__ __forceinline__ void tiles_select(const typename Op::acc_t (&acc)[NT], float (&thr)[NT],
-                                                    typename Op::gate_t (&gt)[NT], float (&ld)[NT][KP], int (&li)[NT][KP],
-                                                    int row0, int h, const uint32_t *parity)
+template <class Op, int KP, int NT, bool PL>
+static __device__ __forceinline__ void tiles_select(AccArr<Op, NT> &acc,
+                                                    float (&thr)[lists_per_lane<PL, NT>()],
+                                                    typename Op::gate_t (&gt)[lists_per_lane<PL, NT>()],
+                                                    typename Op::gate_t (&gq)[NT],
+                                                    float (&ld)[lists_per_lane<PL, NT>()][KP],
+                                                    int (&li)[lists_per_lane<PL, NT>()][KP], int row0, int h,
+                                                    const uint32_t *parity)
 {
     bool any[NT];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) any[nt] = __builtin_amdgcn_ballot_w64(Op::gate_min(acc[nt]) < gt[nt]) != 0;
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
-        if (__builtin_expect(any[nt], 0)) tile_insert<Op, KP>(acc[nt], thr[nt], gt[nt], ld[nt], li[nt], row0, h, parity);
+    gate_any<Op, NT, PL>(acc, gt, gq, any);
+    gate_insert<Op, KP, NT, PL>(acc, any, thr, gt, gq, ld, li, row0, h, parity);
 }
 
 
@@ -726,13 +838,13 @@ static __device__ __forceinline__ void tile_reads(const uint4 *frag, const float
 // gate of the previous tile (acc_old), scheduled as one block: all LDS reads
 // of the new tile first, then MFMAs interleaved with the gate's vector ops.
 // Insertions for the previous tile (rare) follow after the block.
-template <class Op, int KP, int NT>
-static __device__ __forceinline__ void pipe_step(typename Op::acc_t (&acc_new)[NT],
-                                                 const typename Op::acc_t (&acc_old)[NT],
+template <class Op, int KP, int NT, bool PL, int NL = lists_per_lane<PL, NT>()>
+static __device__ __forceinline__ void pipe_step(AccArr<Op, NT> &acc_new, AccArr<Op, NT> &acc_old,
                                                  const uint4 (&bq)[NT][Op::kSteps][Op::kBU], const int (&sb)[NT],
                                                  const uint4 *frag, const float4 *seed, const int32_t *rsc, int lane,
-                                                 int h, float (&thr)[NT], typename Op::gate_t (&gt)[NT], float (&ld)[NT][KP],
-                                                 int (&li)[NT][KP], int row_old, const uint32_t *parity)
+                                                 int h, float (&thr)[NL], typename Op::gate_t (&gt)[NL],
+                                                 typename Op::gate_t (&gq)[NT], float (&ld)[NL][KP],
+                                                 int (&li)[NL][KP], int row_old, const uint32_t *parity)
 {
     using acc_t = typename Op::acc_t;
     constexpr int S = Op::kSteps;
@@ -743,8 +855,7 @@ static __device__ __forceinline__ void pipe_step(typename Op::acc_t (&acc_new)[N
     tile_reads<Op>(frag, seed, rsc, lane, h, av, sd, sa);
     const acc_t seed_acc = __builtin_bit_cast(acc_t, sd);
     bool any[NT];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) any[nt] = __builtin_amdgcn_ballot_w64(Op::gate_min(acc_old[nt]) < gt[nt]) != 0;
+    gate_any<Op, NT, PL>(acc_old, gt, gq, any);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
 #pragma unroll
@@ -756,9 +867,7 @@ static __device__ __forceinline__ void pipe_step(typename Op::acc_t (&acc_new)[N
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);     // one MFMA
         __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);     // up to two vector ops
     }
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
-        if (__builtin_expect(any[nt], 0)) tile_insert<Op, KP>(acc_old[nt], thr[nt], gt[nt], ld[nt], li[nt], row_old, h, parity);
+    gate_insert<Op, KP, NT, PL>(acc_old, any, thr, gt, gq, ld, li, row_old, h, parity);
 }
 
 // Calls f(std::integral_constant<int, I>) for I = B .. E-1 (a loop whose
@@ -818,20 +927,19 @@ static __device__ __forceinline__ void tile_load(const uint4 *frag, const float4
 // One pipeline step on a tile already in registers: its MFMA chain (into
 // acc_new) interleaved with the gate of the previous tile (acc_old); the
 // next tile's LDS loads, issued just before by the caller, lead the block.
-template <class Op, int KP, int NT>
-static __device__ __forceinline__ void pipe_step_regs(typename Op::acc_t (&acc_new)[NT],
-                                                      const typename Op::acc_t (&acc_old)[NT],
+template <class Op, int KP, int NT, bool PL, int NL = lists_per_lane<PL, NT>()>
+static __device__ __forceinline__ void pipe_step_regs(AccArr<Op, NT> &acc_new, AccArr<Op, NT> &acc_old,
                                                       const uint4 (&bq)[NT][Op::kSteps][Op::kBU],
                                                       const int (&sb)[NT], const TileRegs<Op> &cur, int h,
-                                                      float (&thr)[NT], typename Op::gate_t (&gt)[NT], float (&ld)[NT][KP],
-                                                      int (&li)[NT][KP], int row_old, const uint32_t *parity)
+                                                      float (&thr)[NL], typename Op::gate_t (&gt)[NL],
+                                                      typename Op::gate_t (&gq)[NT], float (&ld)[NL][KP],
+                                                      int (&li)[NL][KP], int row_old, const uint32_t *parity)
 {
     using acc_t = typename Op::acc_t;
     constexpr int S = Op::kSteps;
     const acc_t seed_acc = __builtin_bit_cast(acc_t, cur.sd);
     bool any[NT];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) any[nt] = __builtin_amdgcn_ballot_w64(Op::gate_min(acc_old[nt]) < gt[nt]) != 0;
+    gate_any<Op, NT, PL>(acc_old, gt, gq, any);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
 #pragma unroll
@@ -856,20 +964,19 @@ static __device__ __forceinline__ void pipe_step_regs(typename Op::acc_t (&acc_n
         __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);     // up to three vector ops
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);     // one MFMA
     }
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
-        if (__builtin_expect(any[nt], 0)) tile_insert<Op, KP>(acc_old[nt], thr[nt], gt[nt], ld[nt], li[nt], row_old, h, parity);
+    gate_insert<Op, KP, NT, PL>(acc_old, any, thr, gt, gq, ld, li, row_old, h, parity);
 }
 
 // Two waves per SIMD (256 registers each), except where the lists need one
-// wave per SIMD (W = 4) and its full register file: the 64-entry lists, and
-// two query tiles of lists longer than 20.
-template <int KP, int NT>
-constexpr int waves_per_simd() { return (KP > 40 || (NT == 2 && KP > 20)) ? 1 : 2; }
+// wave per SIMD (W = 4) and its full register file: 64-entry lists, and two
+// lists per lane longer than 20.
+template <int KP, int NL>
+constexpr int waves_per_simd() { return (KP > 40 || (NL == 2 && KP > 20)) ? 1 : 2; }
 
-template <class Op, int KP, int NT, int MT, int W, int NB>
+template <class Op, int KP, int NT, int MT, int W, int NB, bool PL = false>
 __global__ __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W),
-                          amdgpu_waves_per_eu(waves_per_simd<KP, NT>(), waves_per_simd<KP, NT>())))
+                          amdgpu_waves_per_eu(waves_per_simd<KP, lists_per_lane<PL, NT>()>(),
+                                              waves_per_simd<KP, lists_per_lane<PL, NT>()>())))
 void k_dist_topk(DistArgs a)
 {
     constexpr int S = Op::kSteps;
@@ -877,6 +984,8 @@ void k_dist_topk(DistArgs a)
     constexpr int TILE_U4 = S * AU * 64;          // uint4 per 32-row tile
     constexpr int STAGE_U4 = MT * TILE_U4;
     constexpr int QW = Op::kQT * NT;              // queries per wave
+    constexpr int NL = lists_per_lane<PL, NT>();  // lists per lane
+    static_assert(!PL || (NT == 2 && Op::kQT == 32), "pair lists: two query tiles of 32x32 blocks");
     constexpr int QB = W * QW;                    // queries per workgroup
     constexpr int PD = NB - 1;                    // stages in flight ahead of the one computed
     constexpr int LPS = StageLoads<Op, MT, W>::total;   // loads per wave per stage
@@ -954,22 +1063,39 @@ void k_dist_topk(DistArgs a)
                 Op::load_b(q_src, a.q_scale, qi[nt], qi[nt] < n_q, h, bq[nt], sb[nt]);
             }
 
-            float ld[NT][KP];
-            int li[NT][KP];
-            float thr[NT];
-            typename Op::gate_t gt[NT];
+            // the query of list l, and its partial list's offset
+            auto list_query = [&](int l) -> int64_t {
+                return PL ? qb * QB + wave * QW + h * 32 + col : qi[l];
+            };
+            auto list_base = [&](int l) -> int64_t {
+                return PL ? ((int64_t)slice * a.q_cap + list_query(l)) * KP
+                          : ((int64_t)(slice * Op::kGroups + h) * a.q_cap + qi[l]) * KP;
+            };
+            float ld[NL][KP];
+            int li[NL][KP];
+            float thr[NL];
+            typename Op::gate_t gt[NL];
+            typename Op::gate_t gq[NT];           // pair lists: gate threshold of each query tile's query
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const int64_t base = ((int64_t)(slice * Op::kGroups + h) * a.q_cap + qi[nt]) * KP;
-                const bool load = !Op::kNbnn && c > 0 && qi[nt] < n_q;
+            for (int l = 0; l < NL; ++l) {
+                const int64_t base = list_base(l);
+                const bool load = !Op::kNbnn && c > 0 && list_query(l) < n_q;
 #pragma unroll
                 for (int p = 0; p < KP; ++p) {
-                    ld[nt][p] = load ? a.part_d[base + p] : __builtin_inff();
-                    li[nt][p] = load ? a.part_i[base + p] : -1;
+                    ld[l][p] = load ? a.part_d[base + p] : __builtin_inff();
+                    li[l][p] = load ? a.part_i[base + p] : -1;
                 }
-                thr[nt] = ld[nt][KP - 1];
-                gt[nt] = Op::gate_thr(thr[nt]);
+                thr[l] = ld[l][KP - 1];
+                gt[l] = Op::gate_thr(thr[l]);
             }
+            auto share_gates = [&]() {
+                if constexpr (PL) {
+                    const typename Op::gate_t other = __shfl_xor(gt[0], 32);
+                    gq[0] = h == 0 ? gt[0] : other;
+                    gq[1] = h == 0 ? other : gt[0];
+                }
+            };
+            share_gates();
             // A wave whose stage wait gave up marks its first list with a NaN
             // key in the last slot: its threshold turns NaN, so nothing more
             // is inserted, and the kernels that read the lists (merge, FP8
@@ -989,17 +1115,19 @@ void k_dist_topk(DistArgs a)
                 if constexpr (Op::kNbnn) {
                     if (__builtin_isnan(ld[0][KP - 1]) && lane == 0) atomicOr(a.status, kStatusWaitGaveUp);
 #pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) {
-                        if (qi[nt] < n_q && ld[nt][0] < __builtin_inff())
-                            atomicMin(a.cls_min + (int64_t)cur_cls * a.q_cap + qi[nt], (int)ld[nt][0]);
+                    for (int l = 0; l < NL; ++l) {
+                        const int64_t ql = list_query(l);
+                        if (ql < n_q && ld[l][0] < __builtin_inff())
+                            atomicMin(a.cls_min + (int64_t)cur_cls * a.q_cap + ql, (int)ld[l][0]);
 #pragma unroll
                         for (int p = 0; p < KP; ++p) {
-                            ld[nt][p] = __builtin_inff();
-                            li[nt][p] = -1;
+                            ld[l][p] = __builtin_inff();
+                            li[l][p] = -1;
                         }
-                        thr[nt] = __builtin_inff();
-                        gt[nt] = Op::gate_thr(thr[nt]);
+                        thr[l] = __builtin_inff();
+                        gt[l] = Op::gate_thr(thr[l]);
                     }
+                    share_gates();
                 }
             };
             // The queries and lists are in registers before any stage copy
@@ -1075,7 +1203,7 @@ void k_dist_topk(DistArgs a)
                     }
                     static_for<0, MT>([&](auto M) {
                         constexpr int m = decltype(M)::value;
-                        const int row_t = (int)((t0 + (int64_t)st * MT + m) * kTileRows) + 4 * h;
+                        const int row_t = (int)((t0 + (int64_t)st * MT + m) * kTileRows) + (PL ? 0 : 4 * h);
                         if constexpr (m == kLandedAt) {
                             wait_vmcnt<(PF - 1) * LPS>();   // this wave's share of stage st + 1 landed
                             cnt_signal((st + 1) % NB);
@@ -1093,10 +1221,10 @@ void k_dist_topk(DistArgs a)
                                           tr[(m + 1) % 2]);
                         }
                         if constexpr (m % 2 == 0)
-                            pipe_step_regs<Op, KP, NT>(acc0, acc1, bq, sb, tr[0], h, thr, gt, ld, li, row_prev,
+                            pipe_step_regs<Op, KP, NT, PL>(acc0, acc1, bq, sb, tr[0], h, thr, gt, gq, ld, li, row_prev,
                                                        a.parity);
                         else
-                            pipe_step_regs<Op, KP, NT>(acc1, acc0, bq, sb, tr[1], h, thr, gt, ld, li, row_prev,
+                            pipe_step_regs<Op, KP, NT, PL>(acc1, acc0, bq, sb, tr[1], h, thr, gt, gq, ld, li, row_prev,
                                                        a.parity);
                         // the step of a stage's first tile gated the previous
                         // stage's last tile: a new class starts after it
@@ -1133,7 +1261,7 @@ void k_dist_topk(DistArgs a)
                     }
                     static_for<0, MT>([&](auto M) {
                         constexpr int m = decltype(M)::value;
-                        const int row_t = (int)((t0 + (int64_t)st * MT + m) * kTileRows) + 4 * h;
+                        const int row_t = (int)((t0 + (int64_t)st * MT + m) * kTileRows) + (PL ? 0 : 4 * h);
                         if constexpr (m == MT - 1) {
                             wait_vmcnt<(PD - 1) * LPS>();       // stage st + 1 landed (this wave's part)
                             __builtin_amdgcn_s_waitcnt(0xc07f); // lgkmcnt(0): this wave's reads of stage st done
@@ -1149,10 +1277,10 @@ void k_dist_topk(DistArgs a)
                                           tr[(m + 1) % 2]);
                         }
                         if constexpr (m % 2 == 0)
-                            pipe_step_regs<Op, KP, NT>(acc0, acc1, bq, sb, tr[0], h, thr, gt, ld, li, row_prev,
+                            pipe_step_regs<Op, KP, NT, PL>(acc0, acc1, bq, sb, tr[0], h, thr, gt, gq, ld, li, row_prev,
                                                        a.parity);
                         else
-                            pipe_step_regs<Op, KP, NT>(acc1, acc0, bq, sb, tr[1], h, thr, gt, ld, li, row_prev,
+                            pipe_step_regs<Op, KP, NT, PL>(acc1, acc0, bq, sb, tr[1], h, thr, gt, gq, ld, li, row_prev,
                                                        a.parity);
                         if constexpr (Op::kNbnn && m == 0) {
                             if (st_cls != cur_cls) {
@@ -1176,14 +1304,14 @@ void k_dist_topk(DistArgs a)
                 }
 #pragma unroll
                 for (int m = 0; m < MT; m += 2) {
-                    const int row_t = (int)((t0 + (int64_t)st * MT + m) * kTileRows) + 4 * h;
-                    pipe_step<Op, KP, NT>(acc0, acc1, bq, sb, s_frag[buf] + m * TILE_U4, s_seed[buf] + m * 8,
-                                          s_rsc[buf] + (Op::kScaled ? m * kTileRows : 0), lane, h, thr, gt, ld, li,
-                                          row_prev, a.parity);
-                    pipe_step<Op, KP, NT>(acc1, acc0, bq, sb, s_frag[buf] + (m + 1) * TILE_U4,
-                                          s_seed[buf] + (m + 1) * 8,
-                                          s_rsc[buf] + (Op::kScaled ? (m + 1) * kTileRows : 0), lane, h, thr, gt,
-                                          ld, li, row_t, a.parity);
+                    const int row_t = (int)((t0 + (int64_t)st * MT + m) * kTileRows) + (PL ? 0 : 4 * h);
+                    pipe_step<Op, KP, NT, PL>(acc0, acc1, bq, sb, s_frag[buf] + m * TILE_U4, s_seed[buf] + m * 8,
+                                              s_rsc[buf] + (Op::kScaled ? m * kTileRows : 0), lane, h, thr, gt, gq,
+                                              ld, li, row_prev, a.parity);
+                    pipe_step<Op, KP, NT, PL>(acc1, acc0, bq, sb, s_frag[buf] + (m + 1) * TILE_U4,
+                                              s_seed[buf] + (m + 1) * 8,
+                                              s_rsc[buf] + (Op::kScaled ? (m + 1) * kTileRows : 0), lane, h, thr,
+                                              gt, gq, ld, li, row_t, a.parity);
                     row_prev = row_t + kTileRows;
                 }
                 // Stage st + 1 has landed (this wave's part); after the barrier
@@ -1198,20 +1326,20 @@ void k_dist_topk(DistArgs a)
             }
             wait_vmcnt<0>();                    // drain the loads past the end of the chunk
             __syncthreads();
-            tiles_select<Op, KP, NT>(acc1, thr, gt, ld, li, row_prev, h, a.parity);
+            tiles_select<Op, KP, NT, PL>(acc1, thr, gt, gq, ld, li, row_prev, h, a.parity);
             if constexpr (Op::kNbnn) {
                 nbnn_flush();
                 continue;
             }
 
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                if (qi[nt] < n_q) {
-                    const int64_t base = ((int64_t)(slice * Op::kGroups + h) * a.q_cap + qi[nt]) * KP;
+            for (int l = 0; l < NL; ++l) {
+                if (list_query(l) < n_q) {
+                    const int64_t base = list_base(l);
 #pragma unroll
                     for (int p = 0; p < KP; ++p) {
-                        a.part_d[base + p] = ld[nt][p];
-                        a.part_i[base + p] = li[nt][p];
+                        a.part_d[base + p] = ld[l][p];
+                        a.part_i[base + p] = li[l][p];
                     }
                 }
             }
@@ -1219,10 +1347,10 @@ void k_dist_topk(DistArgs a)
     }
 }
 
-template <class Op, int KP, int NT, int MT, int W, int NB>
+template <class Op, int KP, int NT, int MT, int W, int NB, bool PL = false>
 static void *kernel_ptr()
 {
-    return reinterpret_cast<void *>(&k_dist_topk<Op, KP, NT, MT, W, NB>);
+    return reinterpret_cast<void *>(&k_dist_topk<Op, KP, NT, MT, W, NB, PL>);
 }
 
 template <class Op, int KP>
@@ -1240,8 +1368,20 @@ static void *pick_variant(int v)
             }
         }
         if (v == 11) return kernel_ptr<Op, KP, 1, 8, 8, 3>();
+        // pair lists (one list per query): two query tiles at every list length
+        if constexpr (KP <= 33)
+            if (v == 19) return kernel_ptr<Op, KP, 2, 8, 8, 3, true>();
         return nullptr;
     } else {
+        // pair lists (one list per query, half the list registers): two
+        // query tiles per wave up to 40-entry lists; one wave per SIMD (the
+        // whole register file) for the 40- and 64-entry FP8 candidate lists
+        if constexpr (Op::kSteps * Op::kAU == 4 && KP <= 40)
+            if (v == 16) return kernel_ptr<Op, KP, 2, 8, 8, 4, true>();
+        if constexpr (Op::kSteps * Op::kAU == 8 && KP <= 33)
+            if (v == 17) return kernel_ptr<Op, KP, 2, 4, 8, 4, true>();
+        if constexpr (Op::kFmt == FMT_FP8 && KP > 20)
+            if (v == 18) return kernel_ptr<Op, KP, 2, 8, 4, 3, true>();
         if (v == 0) return kernel_ptr<Op, KP, 1, 2, 4, 4>();
         if constexpr (KP <= 40)
             if (v == 6) return kernel_ptr<Op, KP, 1, 4, 8, 4>();

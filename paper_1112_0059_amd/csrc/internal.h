@@ -10,6 +10,7 @@ namespace lnbnn {
 constexpr int kDim = 128;
 constexpr int kDimLoc = 160;             // location-augmented descriptors (INT8 mode only)
 constexpr int kTileRows = 32;            // rows of one MFMA A tile
+constexpr int kMaxLists = 64;            // partial lists per query a plan may split into
 constexpr int kPadRows = 256;            // index rows are padded to this multiple
 constexpr int kMaxKP = 33;               // k + 1 <= 33
 constexpr int kMaxFp8K = 32;             // FP8 mode re-ranks 4k <= 128 candidates
@@ -36,14 +37,16 @@ struct BatchDesc {
 // A distance-kernel variant: queries per wave = qt * nt, reference tiles
 // per LDS stage = mt, waves per workgroup.  qt is the MFMA output block's
 // query width (32: 32x32 blocks, two lists per query; 16: 16x16 blocks, four
-// lists per query).  The list length the kernel keeps (>= k + 1) is a
-// separate compile-time parameter.
+// lists per query).  pl = 1: the two lanes of a query in a 32x32 block
+// share one list (held by one of them).  The list length the kernel keeps
+// (>= k + 1) is a separate compile-time parameter.
 struct Variant {
     int nt;
     int mt;
     int waves;
     int buffers;    // LDS stages: the kernel keeps buffers - 1 stages in flight
     int qt;
+    int pl;         // 1: one list per query (pair lists), else one per lane group
 };
 
 struct DistArgs {

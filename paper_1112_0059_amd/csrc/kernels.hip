@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs a)
     const int kp = a.k + 1;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n_q;
          q += (int64_t)gridDim.x * blockDim.x) {
-        int heads[64];
+        int heads[kMaxLists];
         bool marked = false;            // a list's last key is NaN: its stage wait gave up
         for (int l = 0; l < a.n_lists; ++l) {
             heads[l] = 0;
@@ -298,29 +298,34 @@ __global__ void k_fill_u64(unsigned long long *p, const BatchDesc *bd, int32_t n
 // Variant table and dispatch
 // ---------------------------------------------------------------------------
 static const Variant kVariants[] = {
-    // nt, mt, waves, buffers, qt
-    {1, 2, 4, 4, 32},   // 0
-    {2, 2, 4, 4, 32},   // 1
-    {2, 4, 4, 2, 32},   // 2
-    {2, 2, 4, 2, 32},   // 3
-    {2, 4, 8, 4, 32},   // 4
-    {2, 2, 8, 8, 32},   // 5
-    {1, 4, 8, 4, 32},   // 6
-    {2, 4, 4, 3, 32},   // 7
-    {2, 8, 8, 4, 32},   // 8  (4 KB tiles only: INT8, FP8)
-    {2, 4, 8, 8, 32},   // 9  (4 KB tiles only: INT8, FP8)
-    {2, 8, 8, 3, 32},   // 10 (160-element INT8 rows only)
-    {1, 8, 8, 3, 32},   // 11 (8-bit formats: INT8 rows of 128 or 160, FP8 lists up to 40)
-    {2, 8, 4, 3, 32},   // 12 (FP8 lists of 40 and 64: one wave per SIMD)
-    {2, 8, 8, 4, 16},   // 13 (16x16 blocks, INT8 rows of 128)
-    {2, 4, 8, 4, 16},   // 14 (16x16 blocks, FP16 / BF16)
-    {4, 8, 8, 4, 16},   // 15 (16x16 blocks, INT8 rows of 128, lists up to 6)
+    // nt, mt, waves, buffers, qt, pl
+    {1, 2, 4, 4, 32, 0},   // 0
+    {2, 2, 4, 4, 32, 0},   // 1
+    {2, 4, 4, 2, 32, 0},   // 2
+    {2, 2, 4, 2, 32, 0},   // 3
+    {2, 4, 8, 4, 32, 0},   // 4
+    {2, 2, 8, 8, 32, 0},   // 5
+    {1, 4, 8, 4, 32, 0},   // 6
+    {2, 4, 4, 3, 32, 0},   // 7
+    {2, 8, 8, 4, 32, 0},   // 8  (4 KB tiles only: INT8, FP8)
+    {2, 4, 8, 8, 32, 0},   // 9  (4 KB tiles only: INT8, FP8)
+    {2, 8, 8, 3, 32, 0},   // 10 (160-element INT8 rows only)
+    {1, 8, 8, 3, 32, 0},   // 11 (8-bit formats: INT8 rows of 128 or 160, FP8 lists up to 40)
+    {2, 8, 4, 3, 32, 0},   // 12 (FP8 lists of 40 and 64: one wave per SIMD)
+    {2, 8, 8, 4, 16, 0},   // 13 (16x16 blocks, INT8 rows of 128)
+    {2, 4, 8, 4, 16, 0},   // 14 (16x16 blocks, FP16 / BF16)
+    {4, 8, 8, 4, 16, 0},   // 15 (16x16 blocks, INT8 rows of 128, lists up to 6)
+    {2, 8, 8, 4, 32, 1},   // 16 (pair lists, 4 KB tiles: INT8, FP8 lists up to 40)
+    {2, 4, 8, 4, 32, 1},   // 17 (pair lists, FP16 / BF16)
+    {2, 8, 4, 3, 32, 1},   // 18 (pair lists, FP8 lists of 40 and 64: one wave per SIMD)
+    {2, 8, 8, 3, 32, 1},   // 19 (pair lists, 160-element INT8 rows)
 };
 static const char *kVariantNames[] = {"w4_nt1_mt2_nb4", "w4_nt2_mt2_nb4", "w4_nt2_mt4_nb2", "w4_nt2_mt2_nb2",
                                       "w8_nt2_mt4_nb4", "w8_nt2_mt2_nb8", "w8_nt1_mt4_nb4", "w4_nt2_mt4_nb3",
                                       "w8_nt2_mt8_nb4", "w8_nt2_mt4_nb8", "w8_nt2_mt8_nb3", "w8_nt1_mt8_nb3",
                                       "w4_nt2_mt8_nb3", "q16_w8_nt2_mt8_nb4", "q16_w8_nt2_mt4_nb4",
-                                      "q16_w8_nt4_mt8_nb4"};
+                                      "q16_w8_nt4_mt8_nb4", "pl_w8_nt2_mt8_nb4", "pl_w8_nt2_mt4_nb4",
+                                      "pl_w4_nt2_mt8_nb3", "pl_w8_nt2_mt8_nb3"};
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int num_variants() { return kNumVariants; }
@@ -349,8 +354,12 @@ bool variant_supports(int v, int fmt, int kp)
     if (b == 0) return false;
     // 5 KB tiles (160-element INT8 rows) split evenly over the waves only
     // in these stage shapes
-    if (fmt == FMT_I8L) return v == 11 || ((v == 2 || v == 7 || v == 10) && b <= 16);
-    if (v == 10) return false;
+    if (fmt == FMT_I8L) return v == 11 || ((v == 2 || v == 7 || v == 10) && b <= 16) || (v == 19 && b <= 33);
+    if (v == 10 || v == 19) return false;
+    // pair lists: one list per query
+    if (v == 16) return (fmt == FMT_I8 || fmt == FMT_I8N || fmt == FMT_FP8) && b <= 40;
+    if (v == 17) return (fmt == FMT_F16 || fmt == FMT_BF16) && b <= 33;
+    if (v == 18) return fmt == FMT_FP8 && b > 20;
     // 16x16 output blocks: INT8 (128-element rows) and the 16-bit formats
     if (v == 13) return (fmt == FMT_I8 || fmt == FMT_I8N) && b <= 16;
     if (v == 14) return (fmt == FMT_F16 || fmt == FMT_BF16) && b <= 16;

@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void k_cand_merge(RerankArgs a)
     const int64_t n_q = a.bd->n_q;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n_q;
          q += (int64_t)gridDim.x * blockDim.x) {
-        int heads[64];
+        int heads[kMaxLists];
         bool marked = false;            // a list's last key is NaN: its stage wait gave up
         for (int l = 0; l < a.n_lists; ++l) {
             heads[l] = 0;

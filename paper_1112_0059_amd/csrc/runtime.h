@@ -22,6 +22,8 @@ namespace lnbnn {
 int set_err(int code, const char *fmt, ...);
 int hip_err(hipError_t e, const char *what);
 bool fault_injected(const char *site);
+bool log_enabled();
+void log_line(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
 
 #define LN_HIP(expr)                                   \
     do {                                               \

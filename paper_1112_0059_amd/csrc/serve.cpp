@@ -60,6 +60,7 @@ struct Slot {
     int32_t *h_cls = nullptr;
     uint8_t *h_tot = nullptr;
     std::vector<Request *> batch;
+    int64_t batch_desc = 0;        // descriptors of the batch it holds
     int status = LNBNN_OK;
     std::string error;
     bool busy = false;
@@ -85,6 +86,14 @@ struct Server {
     uint64_t next_ticket = 1;
     int64_t next_batch = 0;
     int64_t pending = 0;                  // tickets not yet consumed
+    // memory accounting: the device bytes the slots hold (measured after
+    // they are set up, never more than the index's HBM budget), descriptors
+    // queued and on the device, and the largest batch / in-flight load so far
+    int64_t device_bytes = 0;
+    int64_t queued_desc = 0;
+    int64_t inflight_desc = 0;
+    int64_t peak_batch_desc = 0;
+    int64_t peak_inflight_desc = 0;
 };
 
 static int64_t row_bytes_for_mode(const lnbnn_index *ix, int mode)
@@ -101,9 +110,9 @@ static int64_t slot_bytes(lnbnn_index *ix, int64_t cap, int64_t img_cap)
     int list = 0;
     for (int mode = 0; mode < kNumModes; ++mode)
         if (ix->modes & LNBNN_MODE_BIT(mode)) list = std::max(list, kp_bucket(dist_list_len(mode, kmax), index_fmt(ix, mode)));
-    const int64_t slices = 32;   // upper bound of the plan's split
     int64_t b = cap * row_bytes_for_mode(ix, fp8 ? LNBNN_FP8_RERANK : 0);
-    b += std::max(slices * 2 * cap * (int64_t)list, (int64_t)ix->n_classes * cap) * 8;
+    // partial lists: a plan splits into at most kMaxLists lists per query
+    b += std::max((int64_t)kMaxLists * cap * (int64_t)list, (int64_t)ix->n_classes * cap) * 8;
     b += img_cap * (16 + 8 + ix->n_classes * 16 + 4) + 16;
     if (fp8) b += cap * (kDim + 4) + cap * (int64_t)fp8_candidates(kmax) * 4 + cap * kmax * 12;
     return b;
@@ -258,6 +267,11 @@ static void scheduler(Server *sv)
             sl->batch.push_back(r);
             it = sv->queue.erase(it);
         }
+        sl->batch_desc = sum;
+        sv->queued_desc -= sum;
+        sv->inflight_desc += sum;
+        sv->peak_batch_desc = std::max(sv->peak_batch_desc, sum);
+        sv->peak_inflight_desc = std::max(sv->peak_inflight_desc, sv->inflight_desc);
         sl->busy = true;
         const int64_t bid = sv->next_batch++;
         lock.unlock();
@@ -312,6 +326,8 @@ static void completer(Server *sv)
             r->st.t_done_ns = t_done;
         }
         sl->batch.clear();
+        sv->inflight_desc -= sl->batch_desc;
+        sl->batch_desc = 0;
         sl->busy = false;
         sv->inflight.pop_front();
         sv->cv.notify_all();
@@ -350,6 +366,23 @@ static int server_start(lnbnn_index *ix)
             return set_err(rc, "%s", msg.c_str());
         }
     }
+    // the budget holds for what was actually allocated, not only for the
+    // estimate that chose the capacity
+    int64_t held = 0;
+    for (Slot *sl : sv->slots) held += sl->ws.bytes();
+    if (held > ix->hbm_budget) {
+        for (Slot *d : sv->slots) {
+            free_slot(d);
+            delete d;
+        }
+        sv->slots.clear();
+        if (auto_cap) sv->max_batch_desc = 0;
+        return set_err(LNBNN_ENOMEM, "serving slots hold %lld bytes, above the HBM budget of %lld",
+                       (long long)held, (long long)ix->hbm_budget);
+    }
+    sv->device_bytes = held;
+    log_line("serving started: %d slots of %lld descriptors / %d images, %lld device bytes of a %lld-byte budget",
+             sv->n_slots, (long long)sv->max_batch_desc, sv->max_images, (long long)held, (long long)ix->hbm_budget);
     sv->sched = std::thread(scheduler, sv);
     sv->compl_thr = std::thread(completer, sv);
     sv->started = true;
@@ -406,6 +439,29 @@ extern "C" int lnbnn_serve_config(lnbnn_index *ix, int64_t max_batch_desc, int32
     return LNBNN_OK;
 }
 
+extern "C" int lnbnn_serve_info(lnbnn_index *ix, lnbnn_serve_stats *out)
+{
+    if (!ix || !out) return set_err(LNBNN_EINVAL, "NULL argument");
+    *out = lnbnn_serve_stats{};
+    out->hbm_budget = ix->hbm_budget;
+    std::lock_guard<std::mutex> lock(ix->server_mu);
+    Server *sv = ix->server;
+    if (!sv || !sv->started) return LNBNN_OK;
+    std::lock_guard<std::mutex> l2(sv->mu);
+    out->started = 1;
+    out->slots = sv->n_slots;
+    out->device_bytes = sv->device_bytes;
+    out->batch_desc_cap = sv->max_batch_desc;
+    out->max_images = sv->max_images;
+    out->queued_requests = (int64_t)sv->queue.size();
+    out->queued_desc = sv->queued_desc;
+    out->inflight_batches = (int32_t)sv->inflight.size();
+    out->inflight_desc = sv->inflight_desc;
+    out->peak_batch_desc = sv->peak_batch_desc;
+    out->peak_inflight_desc = sv->peak_inflight_desc;
+    return LNBNN_OK;
+}
+
 extern "C" int lnbnn_submit(lnbnn_index *ix, const void *queries, int dtype, int64_t n_desc, int32_t k, int mode,
                             uint64_t *ticket)
 {
@@ -445,6 +501,7 @@ extern "C" int lnbnn_submit(lnbnn_index *ix, const void *queries, int dtype, int
         r->ticket = sv->next_ticket++;
         sv->reqs[r->ticket] = r;
         sv->queue.push_back(r);
+        sv->queued_desc += n_desc;
         sv->pending += 1;
         *ticket = r->ticket;
     }

@@ -108,7 +108,7 @@ def test_tuning_cache_entries_decode():
         cache = json.load(f)
     assert cache
     n = L.lnbnn_num_variants()
-    loc_shapes = {"w4_nt2_mt4_nb2", "w4_nt2_mt4_nb3", "w8_nt2_mt8_nb3", "w8_nt1_mt8_nb3"}
+    loc_shapes = {"w4_nt2_mt4_nb2", "w4_nt2_mt4_nb3", "w8_nt2_mt8_nb3", "w8_nt1_mt8_nb3", "pl_w8_nt2_mt8_nb3"}
     for key, val in cache.items():
         fields = dict(kv.split("=") for kv in key.split(","))
         assert set(fields) == {"arch", "n_refs", "dim", "kp", "mode"}, key

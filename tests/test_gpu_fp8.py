@@ -184,7 +184,39 @@ def test_fp8_alone_equals_in_mix(small):
         assert np.array_equal(alone[2], batch[2][s:e]) and np.array_equal(alone[3], batch[3][s:e])
 
 
-@pytest.mark.parametrize("variant", [0, 6, 11, 12])
+@pytest.mark.parametrize("k", [1, 5, 10, 16, 20])
+def test_fp8_pair_lists_identical(small, k):
+    """The pair-list variants (one candidate list per query) keep the same
+    exact FP8 top 4k as the per-half lists, so every result is bit-identical
+    to the default variant's, with whole-slice sweeps and with few
+    workgroups walking 8-tile chunks; the union-of-halves rule refuses them."""
+    cfg, R, labels, Q, off, ix, want = small
+    base = L.lnbnn_classify(ix, Q, off, k, FP8, want_neighbours=True)
+    ran = 0
+    for v in (16, 18):
+        for chunk, wg in ((0, 0), (8, 3)):
+            try:
+                L.lnbnn_set_tuning(ix, FP8, k, variant=v, chunk_tiles=chunk, max_workgroups=wg)
+            except L.LnbnnError:
+                # two waves per SIMD: lists up to 40; one wave per SIMD: lists above 20
+                assert (v == 16 and 4 * k > 40) or (v == 18 and 4 * k <= 20)
+                continue
+            try:
+                _say(f"fp8 pair lists k={k} variant {v} chunk={chunk}")
+                got = L.lnbnn_classify(ix, Q, off, k, FP8, want_neighbours=True, flags=L.LNBNN_TIMING)
+                assert L.lnbnn_last_timing(ix)["tile_variant"] == v
+            finally:
+                L.lnbnn_set_tuning(ix, FP8, k)
+            for x, y in zip(base, got):
+                assert np.array_equal(x, y)
+            ran += 1
+    assert ran >= 2
+    with pytest.raises(L.LnbnnError) as e:
+        L.lnbnn_set_tuning(ix, FP8_2K, k, variant=18)
+    assert e.value.code == L.LNBNN_EINVAL
+
+
+@pytest.mark.parametrize("variant", [0, 6, 11, 12, 16, 18])
 def test_fp8_variants_and_chunks(small, variant):
     cfg, R, labels, Q, off, ix, want = small
     base = L.lnbnn_classify(ix, Q, off, 10, FP8, want_neighbours=True)

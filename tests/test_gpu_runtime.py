@@ -194,3 +194,37 @@ def test_per_image_timing_covers_every_launch(tiny):
         assert t["total_ms"] >= t["dist_kernel_ms"] > 0
     finally:
         ix.free()
+
+
+def test_environment_settings(tiny, tmp_path, capfd):
+    """LNBNN_HBM_BUDGET sets the serving budget of an index built with
+    budget 0; LNBNN_TUNE_CACHE is the cache lnbnn_autotune uses without a
+    path; LNBNN_LOG=1 writes one line per build, graph capture, tuner
+    decision and serving start to stderr."""
+    import json
+    import torch
+    cfg, R, labels, Q, off, (wt, wc, _, _) = tiny
+    cache = str(tmp_path / "env_cache.json")
+    env = {"LNBNN_HBM_BUDGET": "96M", "LNBNN_TUNE_CACHE": cache, "LNBNN_LOG": "1"}
+    os.environ.update(env)
+    try:
+        ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(I8))
+        try:
+            assert L.lnbnn_serve_info(ix)["hbm_budget"] == 96 << 20
+            v = L.lnbnn_autotune(ix, torch.from_numpy(Q).cuda(), off, 10, I8)
+            with open(cache) as f:
+                entries = json.load(f)
+            assert len(entries) == 1 and (next(iter(entries.values())) & 0xFF) == v
+            cls, tot, _, _ = L.lnbnn_classify(ix, Q, off, 10, I8)
+            assert np.array_equal(tot, wt) and np.array_equal(cls, wc)
+            c, t, _ = _wait(ix, L.lnbnn_submit(ix, Q[off[2]:off[3]], 10, I8))
+            assert c == wc[2] and np.array_equal(t, wt[2])
+        finally:
+            ix.free()
+    finally:
+        for name in env:
+            del os.environ[name]
+    err = capfd.readouterr().err
+    lines = [ln for ln in err.splitlines() if ln.startswith("[lnbnn]")]
+    for what in ("index built", "tuner:", "graph captured", "serving started"):
+        assert any(what in ln for ln in lines), (what, lines)

@@ -160,3 +160,50 @@ def test_serving_exact_k32_matches_classify():
             assert c == want_c[i] and np.array_equal(tot, want_t[i])
     finally:
         ix.free()
+
+
+def test_serving_memory_budget_holds_under_load():
+    """A small HBM budget (160 MiB, room for two slots of 4096 descriptors
+    with lists for every k): the loop picks
+    the batch capacity that fits it, the slots' measured workspace bytes stay
+    within it, and while 120 requests of mixed sizes are queued and on the
+    device no batch exceeds the capacity and no more than slots x capacity
+    descriptors are in flight; a request above the capacity is refused with
+    ENOMEM; every result equals the oracle."""
+    cfg = synth.CONFIGS["T"]
+    R, labels = synth.gen_index(cfg)
+    budget = 160 << 20
+    ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(F16), hbm_budget_bytes=budget)
+    try:
+        info = L.lnbnn_serve_info(ix)
+        assert info["started"] == 0 and info["hbm_budget"] == budget
+        _, counts = synth.request_stream(120, 1000.0, median=600, lo=1, hi=4000)
+        Q, off = synth.gen_requests(cfg, counts)
+        tickets = [L.lnbnn_submit(ix, Q[off[i]:off[i + 1]], 10, F16) for i in range(len(off) - 1)]
+        info = L.lnbnn_serve_info(ix)
+        _say(f"serving: {info}")
+        assert info["started"] == 1 and 0 < info["device_bytes"] <= budget
+        cap, slots = info["batch_desc_cap"], info["slots"]
+        assert cap >= 4000 and cap < (1 << 17)          # the budget, not the default, set it
+        with pytest.raises(L.LnbnnError) as e:
+            L.lnbnn_submit(ix, np.zeros((cap + 1, 128), np.uint8), 10, F16)
+        assert e.value.code == L.LNBNN_ENOMEM
+        results = {}
+        while len(results) < len(tickets):
+            info = L.lnbnn_serve_info(ix)
+            assert info["device_bytes"] <= budget
+            assert info["inflight_desc"] <= slots * cap and info["inflight_batches"] <= slots
+            for i, t in enumerate(tickets):
+                if i not in results:
+                    r = L.lnbnn_poll(ix, t)
+                    if r is not None:
+                        results[i] = r
+            time.sleep(0.0005)
+        info = L.lnbnn_serve_info(ix)
+        assert 0 < info["peak_batch_desc"] <= cap and info["peak_inflight_desc"] <= slots * cap
+        assert info["queued_desc"] == 0 and info["inflight_desc"] == 0
+        want_t, want_c, _, _ = oracle.classify(Q, R, labels, cfg.n_classes, off, 10)
+        for i, (c, tot, _) in results.items():
+            assert c == want_c[i] and np.array_equal(tot, want_t[i])
+    finally:
+        ix.free()
