@@ -973,7 +973,7 @@ static __device__ __forceinline__ void pipe_step_regs(AccArr<Op, NT> &acc_new, A
 template <int KP, int NL>
 constexpr int waves_per_simd() { return (KP > 40 || (NL == 2 && KP > 20)) ? 1 : 2; }
 
-template <class Op, int KP, int NT, int MT, int W, int NB, bool PL = false>
+template <class Op, int KP, int NT, int MT, int W, int NB, bool PL = false, int PFM = 0>
 __global__ __attribute__((amdgpu_flat_work_group_size(64 * W, 64 * W),
                           amdgpu_waves_per_eu(waves_per_simd<KP, lists_per_lane<PL, NT>()>(),
                                               waves_per_simd<KP, lists_per_lane<PL, NT>()>())))
@@ -989,7 +989,9 @@ void k_dist_topk(DistArgs a)
     constexpr int QB = W * QW;                    // queries per workgroup
     constexpr int PD = NB - 1;                    // stages in flight ahead of the one computed
     constexpr int LPS = StageLoads<Op, MT, W>::total;   // loads per wave per stage
-    constexpr bool kPrefetch = Op::kSteps * Op::kAU <= 5;      // 4-5 KB tiles leave registers for it
+    // next-tile prefetch: by default where the tiles are 4-5 KB (they leave
+    // registers for it); PFM > 0 asks for it, PFM < 0 declines it
+    constexpr bool kPrefetch = PFM > 0 || (PFM == 0 && Op::kSteps * Op::kAU <= 5);
     // With 3+ buffers the 8-bit-tile path synchronises per buffer instead of
     // per stage: PF = NB - 2 stages in flight leave one stage of slack, so a
     // wave that inserts delays only itself.
@@ -1347,10 +1349,10 @@ void k_dist_topk(DistArgs a)
     }
 }
 
-template <class Op, int KP, int NT, int MT, int W, int NB, bool PL = false>
+template <class Op, int KP, int NT, int MT, int W, int NB, bool PL = false, int PFM = 0>
 static void *kernel_ptr()
 {
-    return reinterpret_cast<void *>(&k_dist_topk<Op, KP, NT, MT, W, NB, PL>);
+    return reinterpret_cast<void *>(&k_dist_topk<Op, KP, NT, MT, W, NB, PL, PFM>);
 }
 
 template <class Op, int KP>
@@ -1378,8 +1380,17 @@ static void *pick_variant(int v)
         // whole register file) for the 40- and 64-entry FP8 candidate lists
         if constexpr (Op::kSteps * Op::kAU == 4 && KP <= 40)
             if (v == 16) return kernel_ptr<Op, KP, 2, 8, 8, 4, true>();
-        if constexpr (Op::kSteps * Op::kAU == 8 && KP <= 33)
+        // FP8 candidate lists of 21..40 without the next-tile prefetch: its
+        // registers go to the lists' insertion path
+        if constexpr (Op::kFmt == FMT_FP8 && KP > 20 && KP <= 40)
+            if (v == 21) return kernel_ptr<Op, KP, 2, 8, 8, 4, true, -1>();
+        if constexpr (Op::kSteps * Op::kAU == 8 && KP <= 33) {
             if (v == 17) return kernel_ptr<Op, KP, 2, 4, 8, 4, true>();
+            // the same with next-tile prefetch (its 8 KB tiles fit the
+            // registers pair lists free; the insertion path spills)
+            if constexpr (KP <= 16)
+                if (v == 20) return kernel_ptr<Op, KP, 2, 4, 8, 4, true, 1>();
+        }
         if constexpr (Op::kFmt == FMT_FP8 && KP > 20)
             if (v == 18) return kernel_ptr<Op, KP, 2, 8, 4, 3, true>();
         if (v == 0) return kernel_ptr<Op, KP, 1, 2, 4, 4>();

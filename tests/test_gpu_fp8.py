@@ -193,13 +193,15 @@ def test_fp8_pair_lists_identical(small, k):
     cfg, R, labels, Q, off, ix, want = small
     base = L.lnbnn_classify(ix, Q, off, k, FP8, want_neighbours=True)
     ran = 0
-    for v in (16, 18):
+    for v in (16, 18, 21):
         for chunk, wg in ((0, 0), (8, 3)):
             try:
                 L.lnbnn_set_tuning(ix, FP8, k, variant=v, chunk_tiles=chunk, max_workgroups=wg)
             except L.LnbnnError:
-                # two waves per SIMD: lists up to 40; one wave per SIMD: lists above 20
-                assert (v == 16 and 4 * k > 40) or (v == 18 and 4 * k <= 20)
+                # two waves per SIMD: lists up to 40; one wave per SIMD: lists
+                # above 20; no prefetch: lists of 21..40
+                assert ((v == 16 and 4 * k > 40) or (v == 18 and 4 * k <= 20)
+                        or (v == 21 and not 20 < 4 * k <= 40))
                 continue
             try:
                 _say(f"fp8 pair lists k={k} variant {v} chunk={chunk}")
@@ -216,7 +218,7 @@ def test_fp8_pair_lists_identical(small, k):
     assert e.value.code == L.LNBNN_EINVAL
 
 
-@pytest.mark.parametrize("variant", [0, 6, 11, 12, 16, 18])
+@pytest.mark.parametrize("variant", [0, 6, 11, 12, 16, 18, 21])
 def test_fp8_variants_and_chunks(small, variant):
     cfg, R, labels, Q, off, ix, want = small
     base = L.lnbnn_classify(ix, Q, off, 10, FP8, want_neighbours=True)
