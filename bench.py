@@ -39,7 +39,7 @@ PEAK_MFMA_FP8_TFLOPS = 5000.0       # MI355X dense FP8 matrix peak
 PEAK_MFMA_I8_TOPS = 5000.0          # MI355X dense INT8 matrix peak (TOP/s)
 METRIC = "query descriptors/s at 15.4M refs k=10, exact vs FP8+rerank; p99 image ms"
 PEAK_HBM_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dist_topk_L_k10_i8_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dist_topk_traffic.json")
 KERNEL_SRC = [os.path.join(ROOT, "paper_1112_0059_amd", "csrc", f) for f in ("dist_topk.h", "dist_inst.hip")]
 TUNING_CACHE = os.path.join(ROOT, "paper_1112_0059_amd", "tuning_cache.json")
 
@@ -57,16 +57,18 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_per_launch():
-    """HBM bytes per launch of the distance kernel from the committed
-    rocprofv3 counter summary, or None when the kernel source changed since
-    the counters were taken."""
+def traffic_per_launch(leg: str):
+    """HBM bytes per launch of one leg's distance kernel (FETCH_SIZE +
+    WRITE_SIZE, scaled by a device copy's reading) from the committed
+    rocprofv3 counter summaries, or None when the kernel sources changed since
+    the counters were taken.  Legs: exact_i8, exact_f16, nbnn, fp8_topk,
+    fp8_2k, loc."""
     try:
         with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
+            t = json.load(f).get(leg)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha256_16") != kernel_hash():
+    if not t or t.get("kernel_sha256_16") != kernel_hash():
         return None
     return t.get("bytes_per_launch")
 
@@ -195,7 +197,7 @@ def exact_leg(args, L, torch, np, synth):
                    "slices": timing["slices"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_I8_TOPS,
                      "unit": "TOP/s", "frac": achieved / PEAK_MFMA_I8_TOPS,
-                     "traffic": traffic_per_launch(), "kernel": "k_dist_topk<OpI8T<4, FMT_I8>, 11, ...>",
+                     "traffic": traffic_per_launch("exact_i8"), "kernel": "k_dist_topk<OpI8T<4, FMT_I8>, 11, ...>",
                      "kernel_ms": k1_ms, "algorithmic_ops_per_launch": flop},
         "accuracy_statistic": float(np.mean(cls == true_cls)),
     }
@@ -215,7 +217,8 @@ def exact_leg(args, L, torch, np, synth):
                             "same_classes_as_local": bool(np.array_equal(clsn, cls)),
                             "accuracy_statistic": float(np.mean(clsn == true_cls)),
                             "roofline": {"bound": "mfma", "achieved": an, "peak": PEAK_MFMA_I8_TOPS,
-                                         "unit": "TOP/s", "frac": an / PEAK_MFMA_I8_TOPS, "kernel_ms": k1n}}
+                                         "unit": "TOP/s", "frac": an / PEAK_MFMA_I8_TOPS, "kernel_ms": k1n,
+                                         "traffic": traffic_per_launch("nbnn")}}
     if not args.no_f16:
         # the same exact classification on the FP16 matrix cores, for context
         steps16 = max(1, min(args.steps, 2))
@@ -227,7 +230,7 @@ def exact_leg(args, L, torch, np, synth):
                             "same_classes_as_i8": bool(np.array_equal(cls16, cls)),
                             "roofline": {"bound": "mfma", "achieved": a16, "peak": PEAK_MFMA_F16_TFLOPS,
                                          "unit": "TFLOP/s", "frac": a16 / PEAK_MFMA_F16_TFLOPS,
-                                         "kernel_ms": k1_16}}
+                                         "kernel_ms": k1_16, "traffic": traffic_per_launch("exact_f16")}}
     return res, ix, R, Q, cfg
 
 
@@ -264,7 +267,8 @@ def loc_leg(args, L, torch, np, synth):
                        "variant": L.lnbnn_variant_name(timing["tile_variant"]), "autotuned": tuned},
             "roofline": {"bound": "mfma", "achieved": a, "peak": PEAK_MFMA_I8_TOPS, "unit": "TOP/s",
                          "frac": a / PEAK_MFMA_I8_TOPS, "kernel": "k_dist_topk<OpI8T<5, FMT_I8L>, 11, ...>",
-                         "kernel_ms": k1_ms, "algorithmic_ops_per_launch": ops},
+                         "kernel_ms": k1_ms, "algorithmic_ops_per_launch": ops,
+                         "traffic": traffic_per_launch("loc")},
             "accuracy_statistic": float(np.mean(cls == true_cls))}
 
 
@@ -353,7 +357,8 @@ def fp8_leg(args, L, torch, np, synth):
                        "autotuned": tuned},
             "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_FP8_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / PEAK_MFMA_FP8_TFLOPS, "kernel": "k_dist_topk (FP8 candidate pass)",
-                         "kernel_ms": k1 * 1e3, "sequence_ms": float(np.mean(tot_ms))},
+                         "kernel_ms": k1 * 1e3, "sequence_ms": float(np.mean(tot_ms)),
+                         "traffic": traffic_per_launch("fp8_topk" if mode == FP8 else "fp8_2k")},
             "quality": fp8_quality(L, torch, np, ix, dq, off, args.k, mode, cfg.n_classes),
             "accuracy_statistic": acc,
         }

@@ -313,18 +313,18 @@ static bool variant_serves(int v, int mode, int fmt, int kp)
     return !(variant(v).pl && mode == LNBNN_FP8_RERANK_2K);
 }
 
-static int default_variant(int fmt, int kp)
+static int default_variant(int mode, int fmt, int kp)
 {
-    // 8-bit formats: 8-tile stages (8 waves x 64 queries, or 32 queries per
-    // wave where the longer lists need the registers)
-    if (fmt == FMT_FP8 || fmt == FMT_I8 || fmt == FMT_I8N)
-        return variant_supports(8, fmt, kp) ? 8 : variant_supports(11, fmt, kp) ? 11 : 0;
-    if (fmt == FMT_I8L) return variant_supports(10, fmt, kp) ? 10 : 11;
-    // 8 waves x 64 queries share each LDS stage (half the reference traffic
-    // of 4-wave workgroups); 32 queries per wave where the longer neighbour
-    // lists need the registers.
-    if (variant_supports(4, fmt, kp)) return 4;
-    return 6;
+    // the shapes the tuner picked on the 15.36M-reference workloads: pair
+    // lists (one list per query) with 8 waves x 64 queries, 8-tile stages
+    // for the 4-5 KB tiles; the FP8 top-4k candidate lists without the
+    // next-tile prefetch; the union-of-halves FP8 rule on per-half lists
+    if (fmt == FMT_I8 || fmt == FMT_I8N) return 16;
+    if (fmt == FMT_I8L) return 19;
+    if (fmt == FMT_F16 || fmt == FMT_BF16) return 17;
+    const int b = kp_bucket(kp, fmt);
+    if (mode == LNBNN_FP8_RERANK_2K) return b <= 20 ? 8 : b <= 40 ? 11 : 0;
+    return b <= 20 ? 16 : b <= 40 ? 21 : 0;
 }
 
 int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_variant, Plan *out)
@@ -339,7 +339,7 @@ int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_varia
         if (it != ix->pinned.end()) tu = it->second;
     }
     int v = forced_variant >= 0 ? forced_variant : tu.variant;
-    if (v < 0) v = default_variant(fmt, kp);
+    if (v < 0) v = default_variant(mode, fmt, kp);
     if (!variant_serves(v, mode, fmt, kp))
         return set_err(LNBNN_EINVAL, "variant %d cannot serve mode %d with k + 1 = %d", v, mode, kp);
     const Variant var = variant(v);
@@ -351,12 +351,31 @@ int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_varia
     int64_t resident = (int64_t)ix->cu_count * bpc;
     if (tu.max_workgroups > 0) resident = std::min<int64_t>(resident, tu.max_workgroups);
     // Split the reference set only when the query blocks alone cannot keep
-    // every workgroup slot busy; each split costs one more partial list per
-    // lane group (the merge takes at most 64 lists per query).
-    int64_t want = 1;
-    if (n_qb < 2 * resident) want = std::min<int64_t>(kMaxLists / groups, (2 * resident + n_qb - 1) / n_qb);
-    int64_t tps = (n_tiles + want - 1) / want;
-    tps = std::max<int64_t>(8, (tps + 7) / 8 * 8);
+    // every workgroup slot busy twice over; each split costs one more
+    // partial list per lane group (the merge takes at most kMaxLists lists
+    // per query).  The split is the one whose (query block, slice) items
+    // fill the resident workgroups most evenly: estimated time = rounds of
+    // items x (tiles per slice + a start-up cost per item), fewest slices on
+    // a tie.
+    auto slice_tiles = [&](int64_t s) {
+        const int64_t t = (n_tiles + s - 1) / s;
+        return std::max<int64_t>(8, (t + 7) / 8 * 8);
+    };
+    int64_t tps = slice_tiles(1);
+    if (n_qb < 2 * resident) {
+        constexpr int64_t kItemStartTiles = 32;
+        double best = 1e300;
+        for (int64_t s = 1; s <= kMaxLists / groups; ++s) {
+            const int64_t t = slice_tiles(s);
+            if ((n_tiles + t - 1) / t != s) continue;          // the same split as a smaller s
+            const int64_t rounds = (n_qb * s + resident - 1) / resident;
+            const double cost = (double)rounds * (double)(t + kItemStartTiles);
+            if (cost < best) {
+                best = cost;
+                tps = t;
+            }
+        }
+    }
     const int64_t S = (n_tiles + tps - 1) / tps;
     out->variant = v;
     out->fmt = fmt;
@@ -1212,6 +1231,7 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
             if (!r && rep > 0) tot += ix->last_timing.dist_kernel_ms;
         }
         *ms = tot / 2;
+        if (!r) log_line("tuner: mode %d, k %d: %s, chunk %d: %.2f ms", mode, k, variant_name(v), chunk, *ms);
         return r;
     };
     // every variant with whole-slice sweeps, then chunk lengths (chunk-major

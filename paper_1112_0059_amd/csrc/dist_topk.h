@@ -1380,10 +1380,14 @@ static void *pick_variant(int v)
         // whole register file) for the 40- and 64-entry FP8 candidate lists
         if constexpr (Op::kSteps * Op::kAU == 4 && KP <= 40)
             if (v == 16) return kernel_ptr<Op, KP, 2, 8, 8, 4, true>();
-        // FP8 candidate lists of 21..40 without the next-tile prefetch: its
-        // registers go to the lists' insertion path
-        if constexpr (Op::kFmt == FMT_FP8 && KP > 20 && KP <= 40)
-            if (v == 21) return kernel_ptr<Op, KP, 2, 8, 8, 4, true, -1>();
+        // 4 KB tiles without the next-tile prefetch: its registers go to the
+        // lists' insertion path (the FP8 candidate lists insert often)
+        if constexpr (Op::kSteps * Op::kAU == 4 && !Op::kNbnn) {
+            if constexpr (KP <= 40)
+                if (v == 21) return kernel_ptr<Op, KP, 2, 8, 8, 4, true, -1>();
+            if constexpr (KP <= 20)
+                if (v == 22) return kernel_ptr<Op, KP, 2, 8, 8, 4, false, -1>();
+        }
         if constexpr (Op::kSteps * Op::kAU == 8 && KP <= 33) {
             if (v == 17) return kernel_ptr<Op, KP, 2, 4, 8, 4, true>();
             // the same with next-tile prefetch (its 8 KB tiles fit the
@@ -1411,8 +1415,9 @@ static void *pick_variant(int v)
                 if (v == 14) return kernel_ptr<Q16, KP, 2, 4, 8, 4>();
             }
         }
-        // two query tiles of long lists, one wave per SIMD: FP8 candidate lists
-        if constexpr (Op::kFmt == FMT_FP8 && KP > 20)
+        // two query tiles of 64-entry lists, one wave per SIMD: FP8 candidate
+        // lists (at 40 entries this shape spills heavily)
+        if constexpr (Op::kFmt == FMT_FP8 && KP > 40)
             if (v == 12) return kernel_ptr<Op, KP, 2, 8, 4, 3>();
         if constexpr (Op::kFmt == FMT_FP8) {
             if constexpr (KP <= 20) {

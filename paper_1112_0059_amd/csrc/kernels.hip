@@ -311,7 +311,7 @@ static const Variant kVariants[] = {
     {2, 4, 8, 8, 32, 0},   // 9  (4 KB tiles only: INT8, FP8)
     {2, 8, 8, 3, 32, 0},   // 10 (160-element INT8 rows only)
     {1, 8, 8, 3, 32, 0},   // 11 (8-bit formats: INT8 rows of 128 or 160, FP8 lists up to 40)
-    {2, 8, 4, 3, 32, 0},   // 12 (FP8 lists of 40 and 64: one wave per SIMD)
+    {2, 8, 4, 3, 32, 0},   // 12 (FP8 lists of 64: one wave per SIMD)
     {2, 8, 8, 4, 16, 0},   // 13 (16x16 blocks, INT8 rows of 128)
     {2, 4, 8, 4, 16, 0},   // 14 (16x16 blocks, FP16 / BF16)
     {4, 8, 8, 4, 16, 0},   // 15 (16x16 blocks, INT8 rows of 128, lists up to 6)
@@ -320,7 +320,8 @@ static const Variant kVariants[] = {
     {2, 8, 4, 3, 32, 1},   // 18 (pair lists, FP8 lists of 40 and 64: one wave per SIMD)
     {2, 8, 8, 3, 32, 1},   // 19 (pair lists, 160-element INT8 rows)
     {2, 4, 8, 4, 32, 1},   // 20 (pair lists + next-tile prefetch, FP16 / BF16)
-    {2, 8, 8, 4, 32, 1},   // 21 (pair lists without next-tile prefetch, FP8 lists of 40)
+    {2, 8, 8, 4, 32, 1},   // 21 (pair lists without next-tile prefetch: INT8, FP8)
+    {2, 8, 8, 4, 32, 0},   // 22 (w8_nt2_mt8_nb4 without next-tile prefetch: INT8, FP8)
 };
 static const char *kVariantNames[] = {"w4_nt1_mt2_nb4", "w4_nt2_mt2_nb4", "w4_nt2_mt4_nb2", "w4_nt2_mt2_nb2",
                                       "w8_nt2_mt4_nb4", "w8_nt2_mt2_nb8", "w8_nt1_mt4_nb4", "w4_nt2_mt4_nb3",
@@ -328,7 +329,7 @@ static const char *kVariantNames[] = {"w4_nt1_mt2_nb4", "w4_nt2_mt2_nb4", "w4_nt
                                       "w4_nt2_mt8_nb3", "q16_w8_nt2_mt8_nb4", "q16_w8_nt2_mt4_nb4",
                                       "q16_w8_nt4_mt8_nb4", "pl_w8_nt2_mt8_nb4", "pl_w8_nt2_mt4_nb4",
                                       "pl_w4_nt2_mt8_nb3", "pl_w8_nt2_mt8_nb3", "plpf_w8_nt2_mt4_nb4",
-                                      "plnp_w8_nt2_mt8_nb4"};
+                                      "plnp_w8_nt2_mt8_nb4", "np_w8_nt2_mt8_nb4"};
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int num_variants() { return kNumVariants; }
@@ -363,13 +364,14 @@ bool variant_supports(int v, int fmt, int kp)
     if (v == 16) return (fmt == FMT_I8 || fmt == FMT_I8N || fmt == FMT_FP8) && b <= 40;
     if (v == 17) return (fmt == FMT_F16 || fmt == FMT_BF16) && b <= 33;
     if (v == 20) return (fmt == FMT_F16 || fmt == FMT_BF16) && b <= 16;
-    if (v == 21) return fmt == FMT_FP8 && b > 20 && b <= 40;
+    if (v == 21) return (fmt == FMT_FP8 && b <= 40) || fmt == FMT_I8;
+    if (v == 22) return (fmt == FMT_FP8 && b <= 20) || (fmt == FMT_I8 && b <= 16);
     if (v == 18) return fmt == FMT_FP8 && b > 20;
     // 16x16 output blocks: INT8 (128-element rows) and the 16-bit formats
     if (v == 13) return (fmt == FMT_I8 || fmt == FMT_I8N) && b <= 16;
     if (v == 14) return (fmt == FMT_F16 || fmt == FMT_BF16) && b <= 16;
     if (v == 15) return (fmt == FMT_I8 || fmt == FMT_I8N) && b <= 6;
-    if (v == 12) return fmt == FMT_FP8 && b > 20;
+    if (v == 12) return fmt == FMT_FP8 && b > 40;
     // one query tile per wave with 8-tile stages: the 4 KB-tile formats
     if (v == 11) return fmt == FMT_I8 || fmt == FMT_I8N || (fmt == FMT_FP8 && b <= 40);
     // the deep stage variants need the 4 KB tiles of the 8-bit formats

@@ -199,9 +199,9 @@ def test_fp8_pair_lists_identical(small, k):
                 L.lnbnn_set_tuning(ix, FP8, k, variant=v, chunk_tiles=chunk, max_workgroups=wg)
             except L.LnbnnError:
                 # two waves per SIMD: lists up to 40; one wave per SIMD: lists
-                # above 20; no prefetch: lists of 21..40
+                # above 20
                 assert ((v == 16 and 4 * k > 40) or (v == 18 and 4 * k <= 20)
-                        or (v == 21 and not 20 < 4 * k <= 40))
+                        or (v == 21 and 4 * k > 40))
                 continue
             try:
                 _say(f"fp8 pair lists k={k} variant {v} chunk={chunk}")
@@ -218,15 +218,32 @@ def test_fp8_pair_lists_identical(small, k):
     assert e.value.code == L.LNBNN_EINVAL
 
 
-@pytest.mark.parametrize("variant", [0, 6, 11, 12, 16, 18, 21])
-def test_fp8_variants_and_chunks(small, variant):
+@pytest.mark.parametrize("variant", [0, 8, 11, 22])
+def test_fp8_2k_rule_variants_identical(small, variant):
+    """The union-of-halves rule on per-half-list variants, among them the one
+    without next-tile prefetch: bit-identical results, whole-slice sweeps
+    and few workgroups walking 8-tile chunks."""
     cfg, R, labels, Q, off, ix, want = small
-    base = L.lnbnn_classify(ix, Q, off, 10, FP8, want_neighbours=True)
-    L.lnbnn_set_tuning(ix, FP8, 10, variant=variant, chunk_tiles=8, max_workgroups=3)
+    base = L.lnbnn_classify(ix, Q, off, 10, FP8_2K, want_neighbours=True)
+    for chunk, wg in ((0, 0), (8, 3)):
+        L.lnbnn_set_tuning(ix, FP8_2K, 10, variant=variant, chunk_tiles=chunk, max_workgroups=wg)
+        try:
+            got = L.lnbnn_classify(ix, Q, off, 10, FP8_2K, want_neighbours=True)
+        finally:
+            L.lnbnn_set_tuning(ix, FP8_2K, 10)
+        for x, y in zip(base, got):
+            assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("variant,k", [(0, 10), (6, 10), (11, 10), (12, 16), (16, 10), (18, 10), (21, 10)])
+def test_fp8_variants_and_chunks(small, variant, k):
+    cfg, R, labels, Q, off, ix, want = small
+    base = L.lnbnn_classify(ix, Q, off, k, FP8, want_neighbours=True)
+    L.lnbnn_set_tuning(ix, FP8, k, variant=variant, chunk_tiles=8, max_workgroups=3)
     try:
-        got = L.lnbnn_classify(ix, Q, off, 10, FP8, want_neighbours=True)
+        got = L.lnbnn_classify(ix, Q, off, k, FP8, want_neighbours=True)
     finally:
-        L.lnbnn_set_tuning(ix, FP8, 10)
+        L.lnbnn_set_tuning(ix, FP8, k)
     for x, y in zip(base, got):
         assert np.array_equal(x, y)
 

@@ -90,7 +90,9 @@ def test_noalloc_refuses_oversize_batch():
     R, labels = synth.gen_index(cfg)
     ix = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(L.LNBNN_EXACT_I8))
     try:
-        n = 400_000                   # partial lists alone exceed 64 MiB
+        # partial lists alone exceed 64 MiB: even one list of 11 entries
+        # (8 bytes each) for each of 10^6 queries is 88 MB
+        n = 1_000_000
         dq = torch.zeros((n, 128), dtype=torch.uint8, device="cuda")
         cls = torch.full((1,), -7, dtype=torch.int32, device="cuda")
         with pytest.raises(L.LnbnnError) as e:
