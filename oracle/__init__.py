@@ -35,23 +35,32 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lnbnn_oracle.c")
-_LIB = os.path.join(_HERE, "liblnbnn_oracle.so")
+# LNBNN_ORACLE_LIB: load another build of the same source (the sanitizer
+# build of the tests)
+_LIB = os.environ.get("LNBNN_ORACLE_LIB") or os.path.join(_HERE, "liblnbnn_oracle.so")
 
 _lib = None
 
 
-def build(force: bool = True) -> str:
+def build(force: bool = True, out: str | None = None, sanitize: bool = False) -> str:
     """Compile the C oracle with gcc (OpenMP; ISO C, so no multiply-add
     contraction: every double operation is rounded as written).  The blocked
     route is compiled for several x86 vector widths and picked at load time;
-    the arithmetic is the same IEEE operations on every width."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O3", "-std=c11", "-ffp-contract=off", "-fopenmp", "-shared",
+    the arithmetic is the same IEEE operations on every width.
+
+    sanitize: an AddressSanitizer + UndefinedBehaviorSanitizer build (any
+    report aborts) into `out`; the process that loads it must preload gcc's
+    libasan."""
+    lib = out or _LIB
+    if force or not os.path.exists(lib):
+        tmp = lib + ".tmp"
+        opt = (["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                "-fno-omit-frame-pointer"] if sanitize else ["-O3"])
+        cmd = ["gcc", *opt, "-std=c11", "-ffp-contract=off", "-fopenmp", "-shared",
                "-fPIC", "-Wall", "-Wextra", _SRC, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib)
+    return lib
 
 
 def _load():

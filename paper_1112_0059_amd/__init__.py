@@ -17,7 +17,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblnbnn.so")
+# LNBNN_LIBRARY: another build of the same sources (the tests' host-sanitizer build)
+LIB_PATH = os.environ.get("LNBNN_LIBRARY") or os.path.join(_HERE, "liblnbnn.so")
 
 # status codes, element types, modes, flags (values of include/lnbnn.h)
 LNBNN_OK, LNBNN_EINVAL, LNBNN_ENOMEM, LNBNN_EDEVICE = 0, -1, -2, -3

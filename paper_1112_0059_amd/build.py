@@ -30,9 +30,15 @@ def instances():
     return re.findall(r"X\((\w+), (\w+), \w+, (\d+)\)", text)
 
 
+# host-code sanitizers: every -fsanitize= applies to the host pass only
+SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+                  "-Xarch_host", "-g"]
+
+
 def _compile(job) -> str:
     src, obj_name, defines = job
-    obj = os.path.join(BUILD, obj_name)
+    obj = os.path.join(BUILD, obj_name) if not os.path.isabs(obj_name) else obj_name
     cmd = ["hipcc", "-x", "hip", *FLAGS, *defines, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -57,6 +63,36 @@ def build(jobs: int = 0) -> str:
     subprocess.run(cmd, check=True)
     os.replace(tmp, OUT)
     return OUT
+
+
+def asan_runtime() -> str:
+    """The AddressSanitizer runtime of the compiler hipcc drives (a process
+    that loads a sanitized build preloads it)."""
+    r = subprocess.run(["hipcc", "--print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+        raise RuntimeError("hipcc's libclang_rt.asan-x86_64.so not found")
+    return path
+
+
+def build_sanitized(out_dir: str) -> str:
+    """liblnbnn.so with its host code built under AddressSanitizer and
+    UndefinedBehaviorSanitizer (device code unchanged), into out_dir: the
+    host sources are recompiled there, the distance-kernel instance objects
+    of the regular build are reused (built first if missing)."""
+    os.makedirs(out_dir, exist_ok=True)
+    inst = [os.path.join(BUILD, f"dist_{tag}_{kp}.o") for tag, _, kp in instances()]
+    if not all(os.path.exists(o) for o in inst):
+        build()
+    work = [(s, os.path.join(out_dir, os.path.splitext(s)[0] + ".o"), SANITIZE_FLAGS) for s in SOURCES]
+    with ThreadPoolExecutor(min(len(work), os.cpu_count() or 4, 16)) as ex:
+        objs = list(ex.map(_compile, work))
+    out = os.path.join(out_dir, "liblnbnn.so")
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-shared-libsan",
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           *objs, *inst, "-o", out, "-lpthread"]
+    subprocess.run(cmd, check=True)
+    return out
 
 
 if __name__ == "__main__":
