@@ -1394,6 +1394,10 @@ static void *pick_variant(int v)
             // registers pair lists free; the insertion path spills)
             if constexpr (KP <= 16)
                 if (v == 20) return kernel_ptr<Op, KP, 2, 4, 8, 4, true, 1>();
+            // other stage shapes: 8-tile stages (half the stage barriers) in
+            // two buffers, and 4-tile stages three deep
+            if (v == 23) return kernel_ptr<Op, KP, 2, 8, 8, 2, true>();
+            if (v == 24) return kernel_ptr<Op, KP, 2, 4, 8, 3, true>();
         }
         if constexpr (Op::kFmt == FMT_FP8 && KP > 20)
             if (v == 18) return kernel_ptr<Op, KP, 2, 8, 4, 3, true>();

@@ -141,7 +141,7 @@ def test_tiny_pair_lists(tiny, mode):
     reference set and few workgroups walking 8-tile chunks."""
     cfg, R, labels, Q, off, ix, ref = tiny
     # 16-bit formats: also the form with next-tile prefetch (lists up to 16)
-    shapes = [17, 20] if mode != L.LNBNN_EXACT_I8 else [16, 21]
+    shapes = [17, 20, 23, 24] if mode != L.LNBNN_EXACT_I8 else [16, 21]
     assert all(L.lnbnn_variant_name(v).startswith(("pl_", "plpf_", "plnp_")) for v in shapes)
     for k in (1, 5, 10, 20, 32):
         want = ref[k] if k in ref else oracle.classify(Q, R, labels, cfg.n_classes, off, k)
