@@ -551,22 +551,36 @@ static int build_nbnn_layout(lnbnn_index *ix, const uint8_t *d_refs, const int32
 {
     if (ix->dim != kDim) return set_err(LNBNN_EINVAL, "the original NBNN mode takes %d-byte descriptors", kDim);
     const int32_t nc = ix->n_classes;
-    std::vector<int64_t> cnt(nc, 0), start(nc + 1, 0);
-    for (int64_t j = 0; j < ix->n_refs; ++j) cnt[hlab[j]] += 1;
-    for (int32_t c = 0; c < nc; ++c) {
-        if (cnt[c] == 0)
+    // Rows sorted by (class, parity of ||r - 128||^2), each (class, parity)
+    // group padded to whole stages: every stage then holds one class and one
+    // parity, so the kernel knows a tile's exact smallest key from its
+    // smallest accumulator value (key = 2 D + parity).
+    std::vector<uint8_t> par(ix->n_refs);
+    {
+        uint8_t *d_par = nullptr;
+        LN_HIP(hipMallocAsync((void **)&d_par, std::max<int64_t>(1, ix->n_refs), s));
+        hipError_t e = launch_row_parity(d_refs, ix->n_refs, kDim, d_par, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(par.data(), d_par, ix->n_refs, hipMemcpyDeviceToHost, s);
+        (void)hipFreeAsync(d_par, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_err(e, "row parity");
+    }
+    std::vector<int64_t> cnt(2 * (size_t)nc, 0), start(2 * (size_t)nc + 1, 0);
+    for (int64_t j = 0; j < ix->n_refs; ++j) cnt[2 * (size_t)hlab[j] + par[j]] += 1;
+    for (int32_t c = 0; c < nc; ++c)
+        if (cnt[2 * c] + cnt[2 * c + 1] == 0)
             return set_err(LNBNN_EINVAL, "the original NBNN mode needs every class to own a reference (class %d has none)",
                            c);
-        start[c + 1] = start[c] + (cnt[c] + kPadRows - 1) / kPadRows * kPadRows;
-    }
-    const int64_t n_nb = start[nc];
+    for (int32_t g = 0; g < 2 * nc; ++g) start[g + 1] = start[g] + (cnt[g] + kPadRows - 1) / kPadRows * kPadRows;
+    const int64_t n_nb = start[2 * nc];
     if (n_nb >= (int64_t)0x7fffffff) return set_err(LNBNN_EINVAL, "class-sorted index too large");
     h.perm.assign(n_nb, -1);
     std::vector<int64_t> next(start.begin(), start.end() - 1);
-    for (int64_t j = 0; j < ix->n_refs; ++j) h.perm[next[hlab[j]]++] = (int32_t)j;
+    for (int64_t j = 0; j < ix->n_refs; ++j) h.perm[next[2 * (size_t)hlab[j] + par[j]]++] = (int32_t)j;
+    // per tile: 2 * class + parity
     h.tile_class.resize(n_nb / kTileRows);
-    for (int32_t c = 0; c < nc; ++c)
-        for (int64_t t = start[c] / kTileRows; t < start[c + 1] / kTileRows; ++t) h.tile_class[t] = c;
+    for (int32_t g = 0; g < 2 * nc; ++g)
+        for (int64_t t = start[g] / kTileRows; t < start[g + 1] / kTileRows; ++t) h.tile_class[t] = g;
     int rc;
     int32_t *d_perm = nullptr, *iseed = nullptr;
     if ((rc = grow(ix, (void **)&ix->tile_class, n_nb / kTileRows, 4))) return rc;

@@ -622,8 +622,28 @@ static __device__ __forceinline__ void gate_insert(AccArr<Op, NT> &acc, const bo
     }
 }
 
+// Original NBNN: one running minimum key per query tile (in mk), no list.
+// Every stage of the class-sorted copy holds one class and one parity of
+// ||r - 128||^2, so the smallest exact key of a tile's rows is
+// 2 x (the smallest accumulator value) + that parity.  Padding rows (seed
+// 2^30) are clamped to 2^28 first: their keys stay above every real key and
+// no sum overflows.  The update sits behind a wave-uniform branch, taken
+// only when some lane improves: written branch-free, the pipelined loop was
+// allocated differently and spilled the query operands.
+template <class Op, int NT>
+static __device__ __forceinline__ void nbnn_tile_min(const AccArr<Op, NT> &acc, typename Op::gate_t (&mk)[NT],
+                                                     int par)
+{
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int key = 2 * min(Op::gate_min(acc[nt]), 1 << 28) + par;
+        if (__builtin_expect(__builtin_amdgcn_ballot_w64(key < mk[nt]) != 0, 0)) mk[nt] = min(mk[nt], key);
+    }
+}
+
 // Gate + insert for the NT query tiles of one reference tile.  All gates
 // are computed before any branch so they can overlap the next MFMA chain.
+// (Original NBNN: the running minimum keys instead.)
 template <class Op, int KP, int NT, bool PL>
 static __device__ __forceinline__ void tiles_select(AccArr<Op, NT> &acc,
                                                     float (&thr)[lists_per_lane<PL, NT>()],
@@ -631,11 +651,15 @@ static __device__ __forceinline__ void tiles_select(AccArr<Op, NT> &acc,
                                                     typename Op::gate_t (&gq)[NT],
                                                     float (&ld)[lists_per_lane<PL, NT>()][KP],
                                                     int (&li)[lists_per_lane<PL, NT>()][KP], int row0, int h,
-                                                    const uint32_t *parity)
+                                                    const uint32_t *parity, int nb_par = 0)
 {
-    bool any[NT];
-    gate_any<Op, NT, PL>(acc, gt, gq, any);
-    gate_insert<Op, KP, NT, PL>(acc, any, thr, gt, gq, ld, li, row0, h, parity);
+    if constexpr (Op::kNbnn) {
+        nbnn_tile_min<Op, NT>(acc, gq, nb_par);
+    } else {
+        bool any[NT];
+        gate_any<Op, NT, PL>(acc, gt, gq, any);
+        gate_insert<Op, KP, NT, PL>(acc, any, thr, gt, gq, ld, li, row0, h, parity);
+    }
 }
 
 
@@ -844,7 +868,8 @@ static __device__ __forceinline__ void pipe_step(AccArr<Op, NT> &acc_new, AccArr
                                                  const uint4 *frag, const float4 *seed, const int32_t *rsc, int lane,
                                                  int h, float (&thr)[NL], typename Op::gate_t (&gt)[NL],
                                                  typename Op::gate_t (&gq)[NT], float (&ld)[NL][KP],
-                                                 int (&li)[NL][KP], int row_old, const uint32_t *parity)
+                                                 int (&li)[NL][KP], int row_old, const uint32_t *parity,
+                                                 int nb_par = 0)
 {
     using acc_t = typename Op::acc_t;
     constexpr int S = Op::kSteps;
@@ -855,7 +880,10 @@ static __device__ __forceinline__ void pipe_step(AccArr<Op, NT> &acc_new, AccArr
     tile_reads<Op>(frag, seed, rsc, lane, h, av, sd, sa);
     const acc_t seed_acc = __builtin_bit_cast(acc_t, sd);
     bool any[NT];
-    gate_any<Op, NT, PL>(acc_old, gt, gq, any);
+    if constexpr (Op::kNbnn)
+        nbnn_tile_min<Op, NT>(acc_old, gq, nb_par);
+    else
+        gate_any<Op, NT, PL>(acc_old, gt, gq, any);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
 #pragma unroll
@@ -867,7 +895,7 @@ static __device__ __forceinline__ void pipe_step(AccArr<Op, NT> &acc_new, AccArr
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);     // one MFMA
         __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);     // up to two vector ops
     }
-    gate_insert<Op, KP, NT, PL>(acc_old, any, thr, gt, gq, ld, li, row_old, h, parity);
+    if constexpr (!Op::kNbnn) gate_insert<Op, KP, NT, PL>(acc_old, any, thr, gt, gq, ld, li, row_old, h, parity);
 }
 
 // Calls f(std::integral_constant<int, I>) for I = B .. E-1 (a loop whose
@@ -933,13 +961,17 @@ static __device__ __forceinline__ void pipe_step_regs(AccArr<Op, NT> &acc_new, A
                                                       const int (&sb)[NT], const TileRegs<Op> &cur, int h,
                                                       float (&thr)[NL], typename Op::gate_t (&gt)[NL],
                                                       typename Op::gate_t (&gq)[NT], float (&ld)[NL][KP],
-                                                      int (&li)[NL][KP], int row_old, const uint32_t *parity)
+                                                      int (&li)[NL][KP], int row_old, const uint32_t *parity,
+                                                      int nb_par = 0)
 {
     using acc_t = typename Op::acc_t;
     constexpr int S = Op::kSteps;
     const acc_t seed_acc = __builtin_bit_cast(acc_t, cur.sd);
     bool any[NT];
-    gate_any<Op, NT, PL>(acc_old, gt, gq, any);
+    if constexpr (Op::kNbnn)
+        nbnn_tile_min<Op, NT>(acc_old, gq, nb_par);
+    else
+        gate_any<Op, NT, PL>(acc_old, gt, gq, any);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
 #pragma unroll
@@ -964,7 +996,7 @@ static __device__ __forceinline__ void pipe_step_regs(AccArr<Op, NT> &acc_new, A
         __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);     // up to three vector ops
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);     // one MFMA
     }
-    gate_insert<Op, KP, NT, PL>(acc_old, any, thr, gt, gq, ld, li, row_old, h, parity);
+    if constexpr (!Op::kNbnn) gate_insert<Op, KP, NT, PL>(acc_old, any, thr, gt, gq, ld, li, row_old, h, parity);
 }
 
 // Two waves per SIMD (256 registers each), except where the lists need one
@@ -1077,7 +1109,9 @@ void k_dist_topk(DistArgs a)
             int li[NL][KP];
             float thr[NL];
             typename Op::gate_t gt[NL];
-            typename Op::gate_t gq[NT];           // pair lists: gate threshold of each query tile's query
+            // pair lists: gate threshold of each query tile's query; original
+            // NBNN: each query tile's running minimum key (lane's row half)
+            typename Op::gate_t gq[NT];
 #pragma unroll
             for (int l = 0; l < NL; ++l) {
                 const int64_t base = list_base(l);
@@ -1109,27 +1143,31 @@ void k_dist_topk(DistArgs a)
                 ld[0][KP - 1] = gave_up ? nan : ld[0][KP - 1];
                 thr[0] = gave_up ? nan : thr[0];
             };
-            // Original NBNN: the class of the entries now in the lists, and
-            // their flush into the per-class minima.
-            int cur_cls = 0;
-            if constexpr (Op::kNbnn) cur_cls = a.tile_class[t0];
+            // Original NBNN: the class (and parity) of the running minima, and
+            // their flush into the per-class minima: the lanes of a query
+            // combine their row shares, one of them takes the atomic minimum.
+            // The stage value is 2 x class + parity; the tiles gated in a
+            // stage's first step belong to the stage before (p_prev).
+            int cur_cls = 0, p_cur = 0, p_prev = 0, enc0 = 0;
+            if constexpr (Op::kNbnn) {
+                enc0 = a.tile_class[t0];
+                cur_cls = enc0 >> 1;
+                p_cur = p_prev = enc0 & 1;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) gq[nt] = 0x7fffffff;
+            }
             auto nbnn_flush = [&]() {
                 if constexpr (Op::kNbnn) {
                     if (__builtin_isnan(ld[0][KP - 1]) && lane == 0) atomicOr(a.status, kStatusWaitGaveUp);
 #pragma unroll
-                    for (int l = 0; l < NL; ++l) {
-                        const int64_t ql = list_query(l);
-                        if (ql < n_q && ld[l][0] < __builtin_inff())
-                            atomicMin(a.cls_min + (int64_t)cur_cls * a.q_cap + ql, (int)ld[l][0]);
+                    for (int nt = 0; nt < NT; ++nt) {
+                        int key = gq[nt];
 #pragma unroll
-                        for (int p = 0; p < KP; ++p) {
-                            ld[l][p] = __builtin_inff();
-                            li[l][p] = -1;
-                        }
-                        thr[l] = __builtin_inff();
-                        gt[l] = Op::gate_thr(thr[l]);
+                        for (int o = Op::kQT; o < 64; o <<= 1) key = min(key, __shfl_xor(key, o));
+                        if (h == 0 && qi[nt] < n_q && key < (1 << 29))
+                            atomicMin(a.cls_min + (int64_t)cur_cls * a.q_cap + qi[nt], key);
+                        gq[nt] = 0x7fffffff;
                     }
-                    share_gates();
                 }
             };
             // The queries and lists are in registers before any stage copy
@@ -1184,15 +1222,17 @@ void k_dist_topk(DistArgs a)
                 // is in registers.
                 TileRegs<Op> tr[2];           // tile m lives in tr[m % 2]
                 tile_load<Op>(s_frag[0], s_seed[0], s_rsc[0], lane, h, tr[0]);
-                // original NBNN: the class of stage st + 1 is loaded during
-                // stage st and read after the stage's last LDS wait, so the
-                // scalar load never adds a wait of its own
-                int st_cls = cur_cls, nx_cls = cur_cls;
+                // original NBNN: the class and parity of stage st + 1 are
+                // loaded during stage st and read after the stage's last LDS
+                // wait, so the scalar load never adds a wait of its own
+                int st_cls = cur_cls, nx_enc = enc0;
                 for (int st = 0; st < n_st; ++st) {
-                    int ld_cls = 0;
+                    int ld_enc = 0;
                     if constexpr (Op::kNbnn) {
-                        st_cls = nx_cls;
-                        ld_cls = a.tile_class[t0 + (int64_t)min(st + 1, n_st - 1) * MT];
+                        st_cls = nx_enc >> 1;
+                        p_prev = p_cur;
+                        p_cur = nx_enc & 1;
+                        ld_enc = a.tile_class[t0 + (int64_t)min(st + 1, n_st - 1) * MT];
                     }
                     {
                         const int sn = st + PF;
@@ -1212,7 +1252,7 @@ void k_dist_topk(DistArgs a)
                         }
                         if constexpr (m == MT - 1) {
                             __builtin_amdgcn_s_waitcnt(0xc07f); // lgkmcnt(0): this wave's reads of stage st done
-                            if constexpr (Op::kNbnn) nx_cls = ld_cls;
+                            if constexpr (Op::kNbnn) nx_enc = ld_enc;
                             cnt_signal(NB + st % NB);
                             const int nb = (st + 1) % NB;
                             mark_if(cnt_wait(nb, (uint32_t)(W * ((st + 1) / NB + 1))));
@@ -1222,12 +1262,13 @@ void k_dist_topk(DistArgs a)
                                           s_rsc[st % NB] + (Op::kScaled ? (m + 1) * kTileRows : 0), lane, h,
                                           tr[(m + 1) % 2]);
                         }
+                        const int nb_par = m == 0 ? p_prev : p_cur;
                         if constexpr (m % 2 == 0)
                             pipe_step_regs<Op, KP, NT, PL>(acc0, acc1, bq, sb, tr[0], h, thr, gt, gq, ld, li, row_prev,
-                                                       a.parity);
+                                                           a.parity, nb_par);
                         else
                             pipe_step_regs<Op, KP, NT, PL>(acc1, acc0, bq, sb, tr[1], h, thr, gt, gq, ld, li, row_prev,
-                                                       a.parity);
+                                                           a.parity, nb_par);
                         // the step of a stage's first tile gated the previous
                         // stage's last tile: a new class starts after it
                         if constexpr (Op::kNbnn && m == 0) {
@@ -1246,12 +1287,14 @@ void k_dist_topk(DistArgs a)
                 // tile can be loaded while that last tile computes.
                 TileRegs<Op> tr[2];           // tile m lives in tr[m % 2]
                 tile_load<Op>(s_frag[0], s_seed[0], s_rsc[0], lane, h, tr[0]);
-                int st_cls = cur_cls, nx_cls = cur_cls;   // as in the counter path above
+                int st_cls = cur_cls, nx_enc = enc0;   // as in the counter path above
                 for (int st = 0; st < n_st; ++st) {
-                    int ld_cls = 0;
+                    int ld_enc = 0;
                     if constexpr (Op::kNbnn) {
-                        st_cls = nx_cls;
-                        ld_cls = a.tile_class[t0 + (int64_t)min(st + 1, n_st - 1) * MT];
+                        st_cls = nx_enc >> 1;
+                        p_prev = p_cur;
+                        p_cur = nx_enc & 1;
+                        ld_enc = a.tile_class[t0 + (int64_t)min(st + 1, n_st - 1) * MT];
                     }
                     {   // stage st + PD goes into the buffer stage st - 1 used
                         const int sn = st + PD;
@@ -1267,7 +1310,7 @@ void k_dist_topk(DistArgs a)
                         if constexpr (m == MT - 1) {
                             wait_vmcnt<(PD - 1) * LPS>();       // stage st + 1 landed (this wave's part)
                             __builtin_amdgcn_s_waitcnt(0xc07f); // lgkmcnt(0): this wave's reads of stage st done
-                            if constexpr (Op::kNbnn) nx_cls = ld_cls;
+                            if constexpr (Op::kNbnn) nx_enc = ld_enc;
                             asm volatile("" ::: "memory");
                             __builtin_amdgcn_s_barrier();
                             asm volatile("" ::: "memory");
@@ -1278,12 +1321,13 @@ void k_dist_topk(DistArgs a)
                                           s_rsc[buf] + (Op::kScaled ? (m + 1) * kTileRows : 0), lane, h,
                                           tr[(m + 1) % 2]);
                         }
+                        const int nb_par = m == 0 ? p_prev : p_cur;
                         if constexpr (m % 2 == 0)
                             pipe_step_regs<Op, KP, NT, PL>(acc0, acc1, bq, sb, tr[0], h, thr, gt, gq, ld, li, row_prev,
-                                                       a.parity);
+                                                           a.parity, nb_par);
                         else
                             pipe_step_regs<Op, KP, NT, PL>(acc1, acc0, bq, sb, tr[1], h, thr, gt, gq, ld, li, row_prev,
-                                                       a.parity);
+                                                           a.parity, nb_par);
                         if constexpr (Op::kNbnn && m == 0) {
                             if (st_cls != cur_cls) {
                                 nbnn_flush();
@@ -1328,7 +1372,7 @@ void k_dist_topk(DistArgs a)
             }
             wait_vmcnt<0>();                    // drain the loads past the end of the chunk
             __syncthreads();
-            tiles_select<Op, KP, NT, PL>(acc1, thr, gt, gq, ld, li, row_prev, h, a.parity);
+            tiles_select<Op, KP, NT, PL>(acc1, thr, gt, gq, ld, li, row_prev, h, a.parity, p_cur);
             if constexpr (Op::kNbnn) {
                 nbnn_flush();
                 continue;

@@ -67,8 +67,10 @@ struct DistArgs {
     int32_t *status;            // bit 0: a bounded stage wait gave up (set by the kernels that
                                 // read the lists, which carry the mark as a NaN key)
     int32_t spin_limit;         // sleep rounds a stage wait allows before it gives up
-    // original NBNN (FMT_I8N): class of every 32-row tile, and the per-class
-    // minimum key of every query, [n_classes][q_cap] (atomic minima)
+    // original NBNN (FMT_I8N): 2 x class + parity of every 32-row tile (the
+    // class-sorted copy holds one class and one parity of ||r - 128||^2 per
+    // stage), and the per-class minimum key of every query,
+    // [n_classes][q_cap] (atomic minima)
     const int32_t *tile_class;
     int32_t *cls_min;
 };
@@ -189,6 +191,8 @@ hipError_t launch_finish(const FinishArgs &a, int64_t q_cap, hipStream_t s);
 hipError_t launch_argmin(const unsigned long long *totals, const BatchDesc *bd, int64_t img_cap,
                          int32_t n_classes, hipStream_t s);
 hipError_t launch_set_i32(int32_t *p, int32_t v, hipStream_t s);
+// per reference row: parity of ||r - 128||^2 (u8 rows, dim a multiple of 16)
+hipError_t launch_row_parity(const uint8_t *refs, int64_t n_refs, int dim, uint8_t *out, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, int64_t stride, int64_t rows, const BatchDesc *bd,
                            hipStream_t s);
 hipError_t launch_nbnn_totals(const NbnnArgs &a, int64_t img_cap, hipStream_t s);

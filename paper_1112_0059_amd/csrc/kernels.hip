@@ -75,6 +75,25 @@ __global__ void k_seed_i8(const uint8_t *__restrict__ refs, int64_t n_refs, int6
     }
 }
 
+// Parity of ||r - 128||^2 per reference row: the same as the parity of the
+// row's byte sum, since x^2 and x have the same parity and 128 is even.
+__global__ void k_row_parity(const uint8_t *__restrict__ refs, int64_t n_refs, int dim, uint8_t *__restrict__ out)
+{
+    for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < n_refs;
+         row += (int64_t)gridDim.x * blockDim.x) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(refs + row * dim);
+        uint32_t x = 0;
+        for (int c = 0; c < dim / 16; ++c) {
+            const uint4 v = p[c];
+            x ^= v.x ^ v.y ^ v.z ^ v.w;
+        }
+        // the parity of the byte sum is the xor of the bytes' low bits
+        x ^= x >> 16;
+        x ^= x >> 8;
+        out[row] = (uint8_t)(x & 1u);
+    }
+}
+
 // Accumulator seed ||r||^2 (an exact integer in FP32), +inf on padding rows
 // so they never enter a neighbour list.
 __global__ void k_seed_u8(const uint8_t *__restrict__ refs, int64_t n_refs, int64_t n_pad,
@@ -510,6 +529,12 @@ hipError_t launch_nbnn_totals(const NbnnArgs &a, int64_t img_cap, hipStream_t s)
 
 // A one-word store as a kernel (a fill node, not a memset node, when the
 // sequence is captured in a graph).
+hipError_t launch_row_parity(const uint8_t *refs, int64_t n_refs, int dim, uint8_t *out, hipStream_t s)
+{
+    k_row_parity<<<grid_for(n_refs, 256, 65536), 256, 0, s>>>(refs, n_refs, dim, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_set_i32(int32_t *p, int32_t v, hipStream_t s)
 {
     k_set_i32<<<1, 64, 0, s>>>(p, v);

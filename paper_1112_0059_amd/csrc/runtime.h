@@ -138,8 +138,9 @@ struct lnbnn_index {
     float *ref_f32 = nullptr;       // FP8 mode: FP32 references for the re-rank
     int32_t *row_scale = nullptr;   // FP8 mode: E8M0 exponent of every padded row
     uint32_t *parity = nullptr;     // INT8 mode: per-tile mask of ||r - 128||^2 parities
-    // original NBNN mode: the class-sorted INT8 copy (every class padded to
-    // 256 rows), its parity masks and the class of each of its tiles
+    // original NBNN mode: the class-sorted INT8 copy (each class's rows
+    // grouped by the parity of ||r - 128||^2, every group padded to 256
+    // rows), its parity masks and 2 x class + parity of each of its tiles
     uint32_t *parity_n = nullptr;
     int32_t *tile_class = nullptr;
     int64_t rows[lnbnn::kNumFmt] = {};   // padded rows of each packed format
