@@ -523,69 +523,100 @@ static __device__ __forceinline__ int lmin(int a, int b) { return min(a, b); }
 template <class Op> using AccT = typename Op::acc_t;
 template <class Op, int NT> using AccArr = typename Op::acc_t[NT];
 
-// Lists each lane keeps: one per query tile, or (PL, pair lists) one for the
+// Lists each lane keeps: one per query tile, or (PL, shared lists) one for the
 // query it owns.
 template <bool PL, int NT>
 constexpr int lists_per_lane() { return PL ? 1 : NT; }
 
-// Pair lists (32x32 blocks, two query tiles).  Lane l owns the list of
-// query (tile h, column l & 31), h = l / 32: one list per query, which sees
-// every row of every tile, instead of one list per row half.  Its values of
-// a tile sit in two lanes (rows 8g + 0..3 in lane l & 31, rows 8g + 4..7 in
-// lane (l & 31) + 32, both in the accumulator of its query tile), so the
-// insertion path first swaps the upper half of tile 0's accumulator with
-// the lower half of tile 1's (v_permlane32_swap, in place: the accumulators
-// are dead after their gate): then every lane holds its own query's rows
-// 8g + i in a0 and 8g + 4 + i in a1.  The gate needs no
-// swap: each lane compares its values of tile nt with the gate threshold of
-// that tile's query (gq[nt]: its own for nt = h, its partner's otherwise).
-template <class Op, int KP>
-static __device__ __forceinline__ void tile_insert_pl(AccT<Op> &a0, AccT<Op> &a1, float &thr,
-                                                      typename Op::gate_t &gt, typename Op::gate_t (&gq)[2],
-                                                      float (&ld)[KP], int (&li)[KP], int row0, int h,
-                                                      const uint32_t *parity)
+// Shared lists: the kGroups lanes of a query (2 with 32x32 blocks, 4 with
+// 16x16) keep one list, held by one of them, over NT = kGroups query tiles:
+// lane l owns the list of query (tile l / kQT, column l % kQT), which sees
+// every row of every tile.  Its values of a tile sit in the kGroups lanes of
+// its column, each in the accumulator of its query tile, so the insertion
+// path first transposes the accumulators across the lane groups in place
+// (the accumulators are dead after their gate): one v_permlane32_swap round
+// for two groups; for four, a v_permlane32_swap round (tiles j, j+2) and a
+// v_permlane16_swap round (tiles 2k, 2k+1).  Then every lane holds its own
+// query's values, acc[j] register r being row kRowStride*(r/4) + 4j + r%4.
+// The gate needs no exchange: each lane compares its values of tile nt with
+// the gate threshold of that tile's query (gq[nt], exchanged after every
+// insertion).
+template <class Op>
+static __device__ __forceinline__ void swap_lanes32(AccT<Op> &x, AccT<Op> &y)
 {
     using E = typename Op::gate_t;                 // accumulator element type
-    static_assert(Op::kQT == 32 && Op::kAccN == 16, "pair lists are built on 32x32 blocks");
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const auto p = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(uint32_t, (E)a0[r]),
-                                                        __builtin_bit_cast(uint32_t, (E)a1[r]), false, false);
-        a0[r] = __builtin_bit_cast(E, (uint32_t)p[0]);
-        a1[r] = __builtin_bit_cast(E, (uint32_t)p[1]);
+    for (int r = 0; r < Op::kAccN; ++r) {
+        const auto p = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(uint32_t, (E)x[r]),
+                                                        __builtin_bit_cast(uint32_t, (E)y[r]), false, false);
+        x[r] = __builtin_bit_cast(E, (uint32_t)p[0]);
+        y[r] = __builtin_bit_cast(E, (uint32_t)p[1]);
+    }
+}
+
+template <class Op>
+static __device__ __forceinline__ void swap_lanes16(AccT<Op> &x, AccT<Op> &y)
+{
+    using E = typename Op::gate_t;
+#pragma unroll
+    for (int r = 0; r < Op::kAccN; ++r) {
+        const auto p = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(uint32_t, (E)x[r]),
+                                                        __builtin_bit_cast(uint32_t, (E)y[r]), false, false);
+        x[r] = __builtin_bit_cast(E, (uint32_t)p[0]);
+        y[r] = __builtin_bit_cast(E, (uint32_t)p[1]);
+    }
+}
+
+// the gate thresholds of the query tiles' queries, from their owner lanes
+template <class Op, int NT>
+static __device__ __forceinline__ void share_gate_thr(typename Op::gate_t gt, typename Op::gate_t (&gq)[NT], int col)
+{
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) gq[nt] = __shfl(gt, Op::kQT * nt + col);
+}
+
+template <class Op, int KP, int NT>
+static __device__ __forceinline__ void tile_insert_pl(AccArr<Op, NT> &acc, float &thr, typename Op::gate_t &gt,
+                                                      typename Op::gate_t (&gq)[NT], float (&ld)[KP], int (&li)[KP],
+                                                      int row0, int col, const uint32_t *parity)
+{
+    static_assert(NT == Op::kGroups && (NT == 2 || NT == 4), "one query tile per lane group");
+    if constexpr (NT == 2) {
+        swap_lanes32<Op>(acc[0], acc[1]);
+    } else {
+        swap_lanes32<Op>(acc[0], acc[2]);
+        swap_lanes32<Op>(acc[1], acc[3]);
+        swap_lanes16<Op>(acc[0], acc[1]);
+        swap_lanes16<Op>(acc[2], acc[3]);
     }
     uint32_t pm = 0;
     if constexpr (Op::kParity) pm = load_uniform(parity, __builtin_amdgcn_readfirstlane(row0 >> 5));
     int base = row0;                               // opaque, as in tile_insert
     asm volatile("" : "+v"(base));
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        if (__builtin_amdgcn_ballot_w64(lmin(Op::group_min(a0, g), Op::group_min(a1, g)) < gt) == 0) continue;
+    for (int g = 0; g < Op::kAccN / 4; ++g) {
+        typename Op::gate_t m = Op::group_min(acc[0], g);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const float v = Op::key_at(a0[4 * g + i], 8 * g + i, pm);
-            const bool take = v < thr;
-            if (__builtin_amdgcn_ballot_w64(take) != 0) {
-                if (take) list_insert<KP>(v, base + 8 * g + i, ld, li, thr);
-            }
-        }
+        for (int j = 1; j < NT; ++j) m = lmin(m, Op::group_min(acc[j], g));
+        if (__builtin_amdgcn_ballot_w64(m < gt) == 0) continue;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const float v = Op::key_at(a1[4 * g + i], 8 * g + 4 + i, pm);
-            const bool take = v < thr;
-            if (__builtin_amdgcn_ballot_w64(take) != 0) {
-                if (take) list_insert<KP>(v, base + 8 * g + 4 + i, ld, li, thr);
+        for (int j = 0; j < NT; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = Op::kRowStride * g + 4 * j + i;
+                const float v = Op::key_at(acc[j][4 * g + i], row, pm);
+                const bool take = v < thr;
+                if (__builtin_amdgcn_ballot_w64(take) != 0) {
+                    if (take) list_insert<KP>(v, base + row, ld, li, thr);
+                }
             }
-        }
     }
     gt = Op::gate_thr(thr);
-    const E other = __shfl_xor(gt, 32);
-    gq[0] = h == 0 ? gt : other;
-    gq[1] = h == 0 ? other : gt;
+    share_gate_thr<Op, NT>(gt, gq, col);
 }
 
 // Gate of the NT query tiles of one reference tile: does some lane hold a
-// value below its list's gate threshold?  (Pair lists: one answer for both
+// value below its list's gate threshold?  (Shared lists: one answer for all
 // tiles, in any[0].)
 template <class Op, int NT, bool PL>
 static __device__ __forceinline__ void gate_any(const typename Op::acc_t (&acc)[NT],
@@ -593,8 +624,12 @@ static __device__ __forceinline__ void gate_any(const typename Op::acc_t (&acc)[
                                                 const typename Op::gate_t (&gq)[NT], bool (&any)[NT])
 {
     if constexpr (PL) {
-        any[0] = __builtin_amdgcn_ballot_w64((Op::gate_min(acc[0]) < gq[0]) | (Op::gate_min(acc[1]) < gq[1])) != 0;
-        any[1] = false;
+        bool below = Op::gate_min(acc[0]) < gq[0];
+#pragma unroll
+        for (int nt = 1; nt < NT; ++nt) below = below | (Op::gate_min(acc[nt]) < gq[nt]);
+        any[0] = __builtin_amdgcn_ballot_w64(below) != 0;
+#pragma unroll
+        for (int nt = 1; nt < NT; ++nt) any[nt] = false;
     } else {
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) any[nt] = __builtin_amdgcn_ballot_w64(Op::gate_min(acc[nt]) < gt[nt]) != 0;
@@ -613,7 +648,8 @@ static __device__ __forceinline__ void gate_insert(AccArr<Op, NT> &acc, const bo
 {
     if constexpr (PL) {
         if (__builtin_expect(any[0], 0))
-            tile_insert_pl<Op, KP>(acc[0], acc[1], thr[0], gt[0], gq, ld[0], li[0], row0, h, parity);
+            tile_insert_pl<Op, KP, NT>(acc, thr[0], gt[0], gq, ld[0], li[0], row0,
+                                       (int)(threadIdx.x & (Op::kQT - 1)), parity);
     } else {
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
@@ -1017,7 +1053,7 @@ void k_dist_topk(DistArgs a)
     constexpr int STAGE_U4 = MT * TILE_U4;
     constexpr int QW = Op::kQT * NT;              // queries per wave
     constexpr int NL = lists_per_lane<PL, NT>();  // lists per lane
-    static_assert(!PL || (NT == 2 && Op::kQT == 32), "pair lists: two query tiles of 32x32 blocks");
+    static_assert(!PL || NT == Op::kGroups, "shared lists: one query tile per lane group");
     constexpr int QB = W * QW;                    // queries per workgroup
     constexpr int PD = NB - 1;                    // stages in flight ahead of the one computed
     constexpr int LPS = StageLoads<Op, MT, W>::total;   // loads per wave per stage
@@ -1099,7 +1135,7 @@ void k_dist_topk(DistArgs a)
 
             // the query of list l, and its partial list's offset
             auto list_query = [&](int l) -> int64_t {
-                return PL ? qb * QB + wave * QW + h * 32 + col : qi[l];
+                return PL ? qb * QB + wave * QW + h * Op::kQT + col : qi[l];
             };
             auto list_base = [&](int l) -> int64_t {
                 return PL ? ((int64_t)slice * a.q_cap + list_query(l)) * KP
@@ -1109,8 +1145,9 @@ void k_dist_topk(DistArgs a)
             int li[NL][KP];
             float thr[NL];
             typename Op::gate_t gt[NL];
-            // pair lists: gate threshold of each query tile's query; original
-            // NBNN: each query tile's running minimum key (lane's row half)
+            // shared lists: gate threshold of each query tile's query;
+            // original NBNN: each query tile's running minimum key (the
+            // lane's share of the rows)
             typename Op::gate_t gq[NT];
 #pragma unroll
             for (int l = 0; l < NL; ++l) {
@@ -1125,11 +1162,7 @@ void k_dist_topk(DistArgs a)
                 gt[l] = Op::gate_thr(thr[l]);
             }
             auto share_gates = [&]() {
-                if constexpr (PL) {
-                    const typename Op::gate_t other = __shfl_xor(gt[0], 32);
-                    gq[0] = h == 0 ? gt[0] : other;
-                    gq[1] = h == 0 ? other : gt[0];
-                }
+                if constexpr (PL) share_gate_thr<Op, NT>(gt[0], gq, col);
             };
             share_gates();
             // A wave whose stage wait gave up marks its first list with a NaN
@@ -1414,12 +1447,12 @@ static void *pick_variant(int v)
             }
         }
         if (v == 11) return kernel_ptr<Op, KP, 1, 8, 8, 3>();
-        // pair lists (one list per query): two query tiles at every list length
+        // shared lists (one list per query): two query tiles at every list length
         if constexpr (KP <= 33)
             if (v == 19) return kernel_ptr<Op, KP, 2, 8, 8, 3, true>();
         return nullptr;
     } else {
-        // pair lists (one list per query, half the list registers): two
+        // shared lists (one list per query, half the list registers): two
         // query tiles per wave up to 40-entry lists; one wave per SIMD (the
         // whole register file) for the 40- and 64-entry FP8 candidate lists
         if constexpr (Op::kSteps * Op::kAU == 4 && KP <= 40)
@@ -1435,7 +1468,7 @@ static void *pick_variant(int v)
         if constexpr (Op::kSteps * Op::kAU == 8 && KP <= 33) {
             if (v == 17) return kernel_ptr<Op, KP, 2, 4, 8, 4, true>();
             // the same with next-tile prefetch (its 8 KB tiles fit the
-            // registers pair lists free; the insertion path spills)
+            // registers shared lists free; the insertion path spills)
             if constexpr (KP <= 16)
                 if (v == 20) return kernel_ptr<Op, KP, 2, 4, 8, 4, true, 1>();
             // other stage shapes: 8-tile stages (half the stage barriers) in
@@ -1454,6 +1487,14 @@ static void *pick_variant(int v)
         // 16x16 output blocks, in the formats that have that form: four
         // lists per query, so shorter ones
         using Q16 = typename Square16<Op>::type;
+        // 16x16 blocks with shared lists: four query tiles, one list per query
+        if constexpr (!std::is_void<Q16>::value && !Op::kNbnn && KP <= 33) {
+            if constexpr (Op::kSteps * Op::kAU == 4) {
+                if (v == 25) return kernel_ptr<Q16, KP, 4, 8, 8, 4, true>();
+            } else {
+                if (v == 26) return kernel_ptr<Q16, KP, 4, 4, 8, 4, true>();
+            }
+        }
         if constexpr (!std::is_void<Q16>::value && KP <= 16) {
             if constexpr (Op::kSteps * Op::kAU == 4) {      // 4 KB tiles
                 if (v == 13) return kernel_ptr<Q16, KP, 2, 8, 8, 4>();

@@ -136,13 +136,15 @@ def test_tiny_16x16_blocks(tiny, mode):
 
 @pytest.mark.parametrize("mode", MODES)
 def test_tiny_pair_lists(tiny, mode):
-    """The pair-list variants (the two lanes of a query share one list, held
-    by one of them): every list length, whole-slice sweeps over a split
-    reference set and few workgroups walking 8-tile chunks."""
+    """The shared-list variants (the two lanes of a query in 32x32 blocks, or
+    the four in 16x16 blocks, share one list held by one of them): every
+    list length, whole-slice sweeps over a split reference set and few
+    workgroups walking 8-tile chunks."""
     cfg, R, labels, Q, off, ix, ref = tiny
     # 16-bit formats: also the form with next-tile prefetch (lists up to 16)
-    shapes = [17, 20, 23, 24] if mode != L.LNBNN_EXACT_I8 else [16, 21]
-    assert all(L.lnbnn_variant_name(v).startswith(("pl_", "plpf_", "plnp_")) for v in shapes)
+    # 16x16 blocks with shared lists: 26 (16-bit), 25 (INT8)
+    shapes = [17, 20, 23, 24, 26] if mode != L.LNBNN_EXACT_I8 else [16, 21, 25]
+    assert all(L.lnbnn_variant_name(v).startswith(("pl_", "plpf_", "plnp_", "plq16_")) for v in shapes)
     for k in (1, 5, 10, 20, 32):
         want = ref[k] if k in ref else oracle.classify(Q, R, labels, cfg.n_classes, off, k)
         for v in shapes:
