@@ -253,7 +253,10 @@ int lnbnn_last_timing(const lnbnn_index *ix, lnbnn_timing *out);
  * LNBNN_DEVICE_PTRS classify without outputs), then chunk lengths of the
  * chunk-major walk (lnbnn_tuning.chunk_tiles) for the two fastest, and keeps
  * the fastest setting for this index, keyed by (arch, n_refs, dim, k bucket,
- * mode).  If `cache_path` is not NULL the choice is merged into that JSON
+ * mode).  The setting applies to batches of comparable size: those whose
+ * capacity (the power of two >= max(descriptors, 1024)) is at least 1/8 of
+ * this batch's; smaller batches (e.g. the serving loop's) keep the default
+ * shapes.  If `cache_path` is not NULL the choice is merged into that JSON
  * file (value = variant | chunk_tiles << 8), and a later call with the same
  * key reads it back instead of timing again.  Results do not depend on the
  * setting: every variant and walk computes the same exact selection.
@@ -267,11 +270,11 @@ int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtype,
 /* Pin a kernel variant for (mode, k) on this index (-1 = heuristic choice). */
 int lnbnn_set_variant(lnbnn_index *ix, int mode, int32_t k, int32_t variant);
 
-/* Full launch tuning for (mode, k) on this index.  variant: kernel variant
- * (-1 = heuristic); chunk_tiles: 32-row reference tiles a workgroup runs for
- * one query block before moving to its next block (0 = default, else a
- * multiple of 8); max_workgroups: cap on the persistent grid (0 = every
- * resident slot).  No setting changes any result. */
+/* Full launch tuning for (mode, k) on this index, for batches of every size.
+ * variant: kernel variant (-1 = heuristic); chunk_tiles: 32-row reference
+ * tiles a workgroup runs for one query block before moving to its next block
+ * (0 = default, else a multiple of 8); max_workgroups: cap on the persistent
+ * grid (0 = every resident slot).  No setting changes any result. */
 typedef struct lnbnn_tuning {
     int32_t variant;
     int32_t chunk_tiles;

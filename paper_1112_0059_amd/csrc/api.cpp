@@ -336,7 +336,7 @@ int make_plan(lnbnn_index *ix, int mode, int kp, int64_t q_cap, int forced_varia
     {
         std::lock_guard<std::mutex> lock(ix->plan_mu);
         auto it = ix->pinned.find({mode, kpb});
-        if (it != ix->pinned.end()) tu = it->second;
+        if (it != ix->pinned.end() && q_cap >= it->second.min_q) tu = it->second.t;
     }
     int v = forced_variant >= 0 ? forced_variant : tu.variant;
     if (v < 0) v = default_variant(mode, fmt, kp);
@@ -1147,7 +1147,7 @@ extern "C" int lnbnn_set_tuning(lnbnn_index *ix, int mode, int32_t k, const lnbn
     if (t->variant < 0 && t->chunk_tiles == 0 && t->max_workgroups == 0)
         ix->pinned.erase({mode, kpb});
     else
-        ix->pinned[{mode, kpb}] = *t;
+        ix->pinned[{mode, kpb}] = lnbnn_index::Pin{*t, 0};
     return LNBNN_OK;
 }
 
@@ -1205,6 +1205,10 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
     }
     const int fmt = index_fmt(ix, mode);
     const int kpb = kp_bucket(dist_list_len(mode, k), fmt);
+    // the setting holds for plans within 8x of this batch's capacity bucket:
+    // the fastest shape for a full batch is not the fastest for serving-size
+    // batches, which keep the defaults
+    const int64_t min_q = cap_bucket(std::max<int64_t>(img_offsets[n_images], 1), 1024) / 8;
     char arch[64] = "gfx";
     {
         hipDeviceProp_t prop;
@@ -1221,7 +1225,7 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
         if (it != m.end() && variant_serves(cv, mode, fmt, dist_list_len(mode, k)) && cc >= 0 && cc % 8 == 0) {
             {
                 std::lock_guard<std::mutex> lock(ix->plan_mu);
-                ix->pinned[{mode, kpb}] = lnbnn_tuning{cv, cc, 0};
+                ix->pinned[{mode, kpb}] = lnbnn_index::Pin{lnbnn_tuning{cv, cc, 0}, min_q};
             }
             if (best_variant) *best_variant = cv;
             log_line("tuner: cache hit %s -> %s, chunk %d", key.str().c_str(), variant_name(cv), cc);
@@ -1277,8 +1281,10 @@ extern "C" int lnbnn_autotune(lnbnn_index *ix, const void *queries_dev, int dtyp
         lnbnn_set_variant(ix, mode, k, -1);
         return rc ? rc : set_err(LNBNN_EINVAL, "no variant can serve mode %d with k = %d", mode, k);
     }
-    lnbnn_tuning bt{best, best_chunk, 0};
-    lnbnn_set_tuning(ix, mode, k, &bt);
+    {
+        std::lock_guard<std::mutex> lock(ix->plan_mu);
+        ix->pinned[{mode, kpb}] = lnbnn_index::Pin{lnbnn_tuning{best, best_chunk, 0}, min_q};
+    }
     if (best_variant) *best_variant = best;
     log_line("tuner: %s -> %s, chunk %d (%.2f ms; %zu variants timed)", key.str().c_str(), variant_name(best),
              best_chunk, best_ms, by_variant.size());

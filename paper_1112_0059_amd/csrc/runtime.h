@@ -149,7 +149,13 @@ struct lnbnn_index {
     std::mutex mu;                                     // classify path (workspace, graphs)
     std::mutex plan_mu;                                // tuning and occupancy caches
     lnbnn::Workspace ws;
-    std::map<std::pair<int, int>, lnbnn_tuning> pinned;   // (mode, kp bucket) -> launch tuning
+    // (mode, kp bucket) -> launch tuning, for plans of at least min_q queries'
+    // capacity (a tuned setting holds for batches of the size it was timed on)
+    struct Pin {
+        lnbnn_tuning t;
+        int64_t min_q;
+    };
+    std::map<std::pair<int, int>, Pin> pinned;
     std::map<std::tuple<int, int, int>, int> occupancy;  // (variant, fmt, kpb) -> blocks/CU
     std::map<std::string, lnbnn::GraphEntry> graphs;
     uint64_t graph_clock = 0;
