@@ -465,9 +465,9 @@ def serving_leg(args, L, torch, np, synth, ix_exact, ix_fp8, mu_exact_qps, out=N
         if Qr is not None:
             r["batched_exact"] = summary(*run_batched(ix_exact, L.LNBNN_EXACT_I8, Qr, offr))
             log(f"serving batched exact: {r['batched_exact']}")
-            if rho == 0.7:
-                r["plain_per_image_exact"] = summary(*run_plain(ix_exact, L.LNBNN_EXACT_I8, Qr, offr))
-                log(f"serving plain exact: {r['plain_per_image_exact']}")
+            # the plain form (one launch per image, no batching) at both loads
+            r["plain_per_image_exact"] = summary(*run_plain(ix_exact, L.LNBNN_EXACT_I8, Qr, offr))
+            log(f"serving plain exact: {r['plain_per_image_exact']}")
         if Qf is not None:
             r["batched_fp8_rerank"] = summary(*run_batched(ix_fp8, L.LNBNN_FP8_RERANK, Qf, offf))
             log(f"serving batched fp8: {r['batched_fp8_rerank']}")
