@@ -61,6 +61,20 @@ def test_autotune_search_pins_and_caches(tmp_path, mode):
             t_hit = time.perf_counter() - t0
             _say(f"cache hit in {t_hit * 1e3:.1f} ms")
             assert v2 == v and t_hit < t_search / 5
+            # the setting holds for batches of comparable size only: a one-image
+            # batch (capacity 1024, below 1/8 of the tuned batch's 16384) runs
+            # the variant an untuned index picks, with the same results
+            one = off[:2]
+            ix3 = L.lnbnn_build_index(R, labels, cfg.n_classes, L.LNBNN_MODE_BIT(mode))
+            try:
+                want = L.lnbnn_classify(ix3, Q[:one[-1]], one, 10, mode, flags=L.LNBNN_TIMING)
+                v_default = L.lnbnn_last_timing(ix3)["tile_variant"]
+            finally:
+                ix3.free()
+            got = L.lnbnn_classify(ix2, Q[:one[-1]], one, 10, mode, flags=L.LNBNN_TIMING)
+            assert L.lnbnn_last_timing(ix2)["tile_variant"] == v_default
+            assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+            _say(f"one-image batch: default variant {L.lnbnn_variant_name(v_default)}")
         finally:
             ix2.free()
     finally:
