@@ -71,16 +71,24 @@ static __device__ __forceinline__ int min16(const i32x16 &a)
     return min(min(mn, m4), a[15]);
 }
 
+// Chains of three-operand minima (v_min3): a two-operand float minimum of
+// raw accumulator values costs two canonicalising v_max first, which a
+// pairwise tree of eight values pays three times (11 vector ops, 6 as chains;
+// INT8: 5 and 4).
 static __device__ __forceinline__ float min8(const f32x8 &a)
 {
-    const float m0 = __builtin_fminf(__builtin_fminf(a[0], a[1]), __builtin_fminf(a[2], a[3]));
-    const float m1 = __builtin_fminf(__builtin_fminf(a[4], a[5]), __builtin_fminf(a[6], a[7]));
-    return __builtin_fminf(m0, m1);
+    const float m0 = __builtin_fminf(__builtin_fminf(a[0], a[1]), a[2]);
+    const float m1 = __builtin_fminf(__builtin_fminf(a[3], a[4]), a[5]);
+    const float m2 = __builtin_fminf(__builtin_fminf(m0, a[6]), a[7]);
+    return __builtin_fminf(m2, m1);
 }
 
 static __device__ __forceinline__ int min8(const i32x8 &a)
 {
-    return min(min(min(a[0], a[1]), min(a[2], a[3])), min(min(a[4], a[5]), min(a[6], a[7])));
+    const int m0 = min(min(a[0], a[1]), a[2]);
+    const int m1 = min(min(a[3], a[4]), a[5]);
+    const int m2 = min(min(m0, a[6]), a[7]);
+    return min(m2, m1);
 }
 
 // Float formats: the accumulator is the ranking key d' itself.  The gate
@@ -320,7 +328,11 @@ using OpI8N = OpI8T<4, FMT_I8N, true>;
 template <class Op>
 static __device__ __forceinline__ int frag_off(int s, int u, int lane)
 {
-    if constexpr (Op::kQT == 16) {
+    if constexpr (Op::kQT == 16 && Op::kScaled) {
+        // FP8: u = 2 * (row block) + (16-byte half); one K step
+        const int g = lane >> 4;
+        return (2 * (g >> 1) + (u & 1)) * 64 + 16 * (u >> 1) + (lane & 15) + 32 * (g & 1);
+    } else if constexpr (Op::kQT == 16) {
         const int g = lane >> 4;
         return (2 * s + (g >> 1)) * 64 + 16 * u + (lane & 15) + 32 * (g & 1);
     } else {
@@ -376,11 +388,9 @@ struct OpI8Q : OpI8T<4, FMT, NBN> {
     }
 };
 
-template <class Base16, bool BF>
-struct OpH16Q : Base16 {
-    static constexpr int kSteps = 4;         // K = 32 per step
-    static constexpr int kAU = 2;
-    static constexpr int kBU = 1;
+// Members of the 16x16 layout shared by the float formats.
+template <class Base>
+struct FloatQ : Base {
     static constexpr int kQT = 16;
     static constexpr int kGroups = 4;
     static constexpr int kAccN = 8;
@@ -394,6 +404,13 @@ struct OpH16Q : Base16 {
         return __builtin_fminf(__builtin_fminf(__builtin_fminf(a[4 * g], a[4 * g + 1]), a[4 * g + 2]), a[4 * g + 3]);
     }
     static __device__ __forceinline__ float key(const f32x8 &acc, int r, uint32_t, int) { return acc[r]; }
+};
+
+template <class Base16, bool BF>
+struct OpH16Q : FloatQ<Base16> {
+    static constexpr int kSteps = 4;         // K = 32 per step
+    static constexpr int kAU = 2;
+    static constexpr int kBU = 1;
     static __device__ __forceinline__ void load_b(const void *q, const int32_t *, int64_t qi, bool ok, int h,
                                                   uint4 (&b)[kSteps][kBU], int &sb)
     {
@@ -426,12 +443,51 @@ struct OpH16Q : Base16 {
     }
 };
 
+// FP8, 16x16 blocks (v_mfma_scale_f32_16x16x128_f8f6f4: the whole K = 128
+// in one instruction per 16-row block).  Lane l supplies 32 codes of row
+// 16 b + (l & 15), K elements 32 (l/16) + e: in the 32x32 packing those are
+// the two 16-byte chunks of K step (l/16)/2 at lane 32 ((l/16) & 1) + 16 b +
+// (l & 15), so both shapes read the same packed index.  The two blocks' E8M0
+// row scales travel in bytes 0 and 1 of one register, picked by the scale
+// byte select of each block's instruction.
+struct OpFP8Q : FloatQ<OpFP8> {
+    static constexpr int kSteps = 1;
+    static constexpr int kAU = 4;            // (row block, 16-byte half)
+    static constexpr int kBU = 2;
+    static __device__ __forceinline__ void load_b(const void *q, const int32_t *qsc, int64_t qi, bool ok, int h,
+                                                  uint4 (&b)[kSteps][kBU], int &sb)
+    {
+        const uint4 *qrow = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(q) + (ok ? qi : 0) * kDim);
+#pragma unroll
+        for (int u = 0; u < kBU; ++u) b[0][u] = ok ? qrow[2 * h + u] : make_uint4(0u, 0u, 0u, 0u);
+        sb = ok ? qsc[qi] : 127;
+    }
+    static __device__ __forceinline__ i32x8 cat(const uint4 &x, const uint4 &y)
+    {
+        i32x8 v;
+        v[0] = (int)x.x; v[1] = (int)x.y; v[2] = (int)x.z; v[3] = (int)x.w;
+        v[4] = (int)y.x; v[5] = (int)y.y; v[6] = (int)y.z; v[7] = (int)y.w;
+        return v;
+    }
+    static __device__ __forceinline__ f32x8 mma(const uint4 (&a)[kAU], const uint4 (&b)[kBU], f32x8 c, int sa,
+                                                int sb)
+    {
+        const i32x8 bv = cat(b[0], b[1]);
+        const f32x4v lo = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+            cat(a[0], a[1]), bv, __builtin_shufflevector(c, c, 0, 1, 2, 3), 0, 0, 0, sa, 0, sb);
+        const f32x4v hi = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+            cat(a[2], a[3]), bv, __builtin_shufflevector(c, c, 4, 5, 6, 7), 0, 0, 1, sa, 0, sb);
+        return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+    }
+};
+
 // The 16x16 form of each operand policy that has one (void: none).
 template <class Op> struct Square16 { using type = void; };
 template <> struct Square16<OpI8> { using type = OpI8Q<FMT_I8, false>; };
 template <> struct Square16<OpI8N> { using type = OpI8Q<FMT_I8N, true>; };
 template <> struct Square16<OpF16> { using type = OpH16Q<OpF16, false>; };
 template <> struct Square16<OpBF16> { using type = OpH16Q<OpBF16, true>; };
+template <> struct Square16<OpFP8> { using type = OpFP8Q; };
 
 // ---------------------------------------------------------------------------
 // K1: distances + top-(k+1).
@@ -785,7 +841,37 @@ static __device__ __forceinline__ void tile_reads(const uint4 *frag, const float
     const uint32_t ea = lds_addr(seed + h);
     u32x4 a0, a1, a2, a3, a4, a5, a6, a7;
     f32x4 s0, s1, s2, s3;
-    if constexpr (Op::kQT == 16) {
+    if constexpr (Op::kQT == 16 && Op::kScaled) {
+        // FP8, 16x16 blocks: (row block b, half j) at byte offset 256 b +
+        // 1024 j from the lane's base; the two blocks' row scales 64 bytes apart
+        static_assert(Op::kSteps == 1 && Op::kAU == 4, "16x16 FP8 layout");
+        const uint32_t ra = lds_addr(rsc + (lane & 15));
+        int r0, r1;
+        asm volatile(
+            "ds_read_b128 %0, %8\n\t"
+            "ds_read_b128 %1, %8 offset:1024\n\t"
+            "ds_read_b128 %2, %8 offset:256\n\t"
+            "ds_read_b128 %3, %8 offset:1280\n\t"
+            "ds_read_b128 %4, %9\n\t"
+            "ds_read_b128 %5, %9 offset:64\n\t"
+            "ds_read_b32 %6, %10\n\t"
+            "ds_read_b32 %7, %10 offset:64\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(a0), "=&v"(a1), "=&v"(a2), "=&v"(a3), "=&v"(s0), "=&v"(s1), "=&v"(r0), "=&v"(r1)
+            : "v"(fa), "v"(ea), "v"(ra)
+            : "memory");
+        av[0][0] = __builtin_bit_cast(uint4, a0);
+        av[0][1] = __builtin_bit_cast(uint4, a1);
+        av[0][2] = __builtin_bit_cast(uint4, a2);
+        av[0][3] = __builtin_bit_cast(uint4, a3);
+        sa = r0 | (r1 << 8);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            sd[j] = s0[j];
+            sd[4 + j] = s1[j];
+        }
+        return;
+    } else if constexpr (Op::kQT == 16) {
         // 16-bit formats, 16x16 blocks: K step s, row block u at byte
         // offset 2048 s + 256 u from the lane's base; the lane's two seed
         // groups are 64 bytes apart
@@ -985,7 +1071,10 @@ static __device__ __forceinline__ void tile_load(const uint4 *frag, const float4
         t.sd[4 * g + 2] = sv.z;
         t.sd[4 * g + 3] = sv.w;
     }
-    t.sa = Op::kScaled ? rsc[lane & 31] : 127;
+    if constexpr (Op::kScaled && Op::kQT == 16)
+        t.sa = rsc[lane & 15] | (rsc[16 + (lane & 15)] << 8);
+    else
+        t.sa = Op::kScaled ? rsc[lane & 31] : 127;
 }
 
 // One pipeline step on a tile already in registers: its MFMA chain (into
@@ -1019,7 +1108,7 @@ static __device__ __forceinline__ void pipe_step_regs(AccArr<Op, NT> &acc_new, A
     // chains have completed when the gate's first vector op issues.
     constexpr int NM = S * NT * Op::kMfma;        // MFMAs of the step
     constexpr int LEAD = LNBNN_GATE_LEAD < NM ? LNBNN_GATE_LEAD : NM;
-    constexpr int NREAD = S * Op::kAU + Op::kAccN / 4 + (Op::kScaled ? 1 : 0);   // next tile's LDS loads
+    constexpr int NREAD = S * Op::kAU + Op::kAccN / 4 + (Op::kScaled ? 32 / Op::kQT : 0);   // next tile's LDS loads
 #if LNBNN_READS_AFTER_LEAD
     __builtin_amdgcn_sched_group_barrier(0x008, LEAD, 0);
     __builtin_amdgcn_sched_group_barrier(0x100, NREAD, 0);
@@ -1495,7 +1584,13 @@ static void *pick_variant(int v)
                 if (v == 26) return kernel_ptr<Q16, KP, 4, 4, 8, 4, true>();
             }
         }
-        if constexpr (!std::is_void<Q16>::value && KP <= 16) {
+        // the FP8 top-4k candidate lists on 16x16 blocks (40 entries at
+        // k = 10), with and without the next-tile prefetch
+        if constexpr (Op::kFmt == FMT_FP8 && KP > 33 && KP <= 40)
+            if (v == 25) return kernel_ptr<Q16, KP, 4, 8, 8, 4, true>();
+        if constexpr (Op::kFmt == FMT_FP8 && KP <= 40)
+            if (v == 27) return kernel_ptr<Q16, KP, 4, 8, 8, 4, true, -1>();
+        if constexpr (!std::is_void<Q16>::value && Op::kFmt != FMT_FP8 && KP <= 16) {
             if constexpr (Op::kSteps * Op::kAU == 4) {      // 4 KB tiles
                 if (v == 13) return kernel_ptr<Q16, KP, 2, 8, 8, 4>();
                 if constexpr (KP <= 6)

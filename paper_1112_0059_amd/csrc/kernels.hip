@@ -343,8 +343,9 @@ static const Variant kVariants[] = {
     {2, 8, 8, 4, 32, 0},   // 22 (w8_nt2_mt8_nb4 without next-tile prefetch: INT8, FP8)
     {2, 8, 8, 2, 32, 1},   // 23 (pair lists, FP16 / BF16, 8-tile stages in two buffers)
     {2, 4, 8, 3, 32, 1},   // 24 (pair lists, FP16 / BF16, 4-tile stages three deep)
-    {4, 8, 8, 4, 16, 1},   // 25 (16x16 blocks, shared lists: INT8 rows of 128)
+    {4, 8, 8, 4, 16, 1},   // 25 (16x16 blocks, shared lists: INT8 rows of 128, FP8 lists up to 40)
     {4, 4, 8, 4, 16, 1},   // 26 (16x16 blocks, shared lists: FP16 / BF16)
+    {4, 8, 8, 4, 16, 1},   // 27 (25 without next-tile prefetch: FP8)
 };
 static const char *kVariantNames[] = {"w4_nt1_mt2_nb4", "w4_nt2_mt2_nb4", "w4_nt2_mt4_nb2", "w4_nt2_mt2_nb2",
                                       "w8_nt2_mt4_nb4", "w8_nt2_mt2_nb8", "w8_nt1_mt4_nb4", "w4_nt2_mt4_nb3",
@@ -353,7 +354,8 @@ static const char *kVariantNames[] = {"w4_nt1_mt2_nb4", "w4_nt2_mt2_nb4", "w4_nt
                                       "q16_w8_nt4_mt8_nb4", "pl_w8_nt2_mt8_nb4", "pl_w8_nt2_mt4_nb4",
                                       "pl_w4_nt2_mt8_nb3", "pl_w8_nt2_mt8_nb3", "plpf_w8_nt2_mt4_nb4",
                                       "plnp_w8_nt2_mt8_nb4", "np_w8_nt2_mt8_nb4", "pl_w8_nt2_mt8_nb2",
-                                      "pl_w8_nt2_mt4_nb3", "plq16_w8_nt4_mt8_nb4", "plq16_w8_nt4_mt4_nb4"};
+                                      "pl_w8_nt2_mt4_nb3", "plq16_w8_nt4_mt8_nb4", "plq16_w8_nt4_mt4_nb4",
+                                      "plq16np_w8_nt4_mt8_nb4"};
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int num_variants() { return kNumVariants; }
@@ -391,7 +393,8 @@ bool variant_supports(int v, int fmt, int kp)
     if (v == 21) return (fmt == FMT_FP8 && b <= 40) || fmt == FMT_I8;
     if (v == 22) return (fmt == FMT_FP8 && b <= 20) || (fmt == FMT_I8 && b <= 16);
     if (v == 23 || v == 24) return (fmt == FMT_F16 || fmt == FMT_BF16) && b <= 33;
-    if (v == 25) return fmt == FMT_I8 && b <= 33;
+    if (v == 25) return (fmt == FMT_I8 && b <= 33) || (fmt == FMT_FP8 && b <= 40);
+    if (v == 27) return fmt == FMT_FP8 && b <= 40;
     if (v == 26) return (fmt == FMT_F16 || fmt == FMT_BF16) && b <= 33;
     if (v == 18) return fmt == FMT_FP8 && b > 20;
     // 16x16 output blocks: INT8 (128-element rows) and the 16-bit formats

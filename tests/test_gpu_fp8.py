@@ -218,6 +218,38 @@ def test_fp8_pair_lists_identical(small, k):
     assert e.value.code == L.LNBNN_EINVAL
 
 
+@pytest.mark.parametrize("k", [1, 5, 10])
+def test_fp8_16x16_blocks(small, k):
+    """The candidate pass on 16x16 blocks (v_mfma_scale_f32_16x16x128_f8f6f4,
+    four query tiles, one 4k list per query), with and without the next-tile
+    prefetch, whole-slice sweeps and few workgroups walking 8-tile chunks.
+    One instruction sums all 128 products where the 32x32 form sums two
+    halves, so an FP8 key may differ in its last place: the results are
+    held to the candidate model and to the FP64 oracle's decisions, not
+    compared bit-for-bit with the 32x32 form."""
+    cfg, R, labels, Q, off, ix, want = small
+    base = L.lnbnn_classify(ix, Q, off, k, FP8, want_neighbours=True)
+    for v in (25, 27):
+        for chunk, wg in ((0, 0), (8, 3)):
+            L.lnbnn_set_tuning(ix, FP8, k, variant=v, chunk_tiles=chunk, max_workgroups=wg)
+            try:
+                _say(f"fp8 16x16 blocks k={k} variant {v} chunk={chunk}")
+                got = L.lnbnn_classify(ix, Q, off, k, FP8, want_neighbours=True, flags=L.LNBNN_TIMING)
+                assert L.lnbnn_last_timing(ix)["tile_variant"] == v
+            finally:
+                L.lnbnn_set_tuning(ix, FP8, k)
+            _check_mechanics(Q, R, got, k)
+            n = model_check(Q, R, got[2], got[3], k, FP8)
+            same = np.all(got[2] == base[2], axis=1).mean()
+            _say(f"decided by the FP8 model and equal to it: {n}/{Q.shape[0]}; lists as the 32x32 form's: {same:.4f}")
+            assert n >= Q.shape[0] // 2
+            _, agree = _compare(got, want[k], labels, off, k, cfg.n_classes)
+            assert agree == 1.0
+    with pytest.raises(L.LnbnnError) as e:
+        L.lnbnn_set_tuning(ix, FP8_2K, k, variant=27)
+    assert e.value.code == L.LNBNN_EINVAL
+
+
 @pytest.mark.parametrize("variant", [0, 8, 11, 22])
 def test_fp8_2k_rule_variants_identical(small, variant):
     """The union-of-halves rule on per-half-list variants, among them the one

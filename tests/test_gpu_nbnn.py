@@ -66,7 +66,7 @@ def test_nbnn_every_variant_and_chunked_walk(tiny):
         try:
             L.lnbnn_set_variant(ix, NB, 10, v)
         except L.LnbnnError:
-            assert v in (10, 12, 14, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26)    # other widths, formats or lists
+            assert v in (10, 12, 14, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27)    # other widths, formats or lists
             continue
         _say(f"nbnn variant {v}")
         _check(L.lnbnn_classify(ix, Q, off, 10, NB), want)
