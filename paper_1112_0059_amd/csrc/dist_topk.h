@@ -49,15 +49,23 @@ static __device__ __forceinline__ uint32_t byte_at(uint2 r, int e)
 // accumulator seeded with ||r~||^2 yields ||r~||^2 - 2 q~.r~ of the
 // dequantised values.
 // ---------------------------------------------------------------------------
+// Float minima of accumulator values use the NaN-propagating minimum
+// (v_minimum3_f32): the accumulators are never NaN (finite FP8/16-bit
+// products, finite or +inf seeds), so it equals the IEEE minNum there, and
+// unlike minNum it takes raw operands without a canonicalising v_max first
+// (16 values: 8 vector ops instead of 10; 8 values: 4 instead of 6).
+static __device__ __forceinline__ float fmin_acc(float a, float b) { return __builtin_elementwise_minimum(a, b); }
+
 static __device__ __forceinline__ float min16(const f32x16 &acc)
 {
-    const float m0 = __builtin_fminf(__builtin_fminf(acc[0], acc[1]), acc[2]);
-    const float m1 = __builtin_fminf(__builtin_fminf(acc[3], acc[4]), acc[5]);
-    const float m2 = __builtin_fminf(__builtin_fminf(acc[6], acc[7]), acc[8]);
-    const float m3 = __builtin_fminf(__builtin_fminf(acc[9], acc[10]), acc[11]);
-    const float m4 = __builtin_fminf(__builtin_fminf(acc[12], acc[13]), acc[14]);
-    float mn = __builtin_fminf(__builtin_fminf(m0, m1), __builtin_fminf(m2, m3));
-    return __builtin_fminf(__builtin_fminf(mn, m4), acc[15]);
+    const float m0 = fmin_acc(fmin_acc(acc[0], acc[1]), acc[2]);
+    const float m1 = fmin_acc(fmin_acc(acc[3], acc[4]), acc[5]);
+    const float m2 = fmin_acc(fmin_acc(acc[6], acc[7]), acc[8]);
+    const float m3 = fmin_acc(fmin_acc(acc[9], acc[10]), acc[11]);
+    const float m4 = fmin_acc(fmin_acc(acc[12], acc[13]), acc[14]);
+    const float m5 = fmin_acc(fmin_acc(m0, m1), acc[15]);
+    const float m6 = fmin_acc(fmin_acc(m2, m3), m4);
+    return fmin_acc(m5, m6);
 }
 
 static __device__ __forceinline__ int min16(const i32x16 &a)
@@ -71,16 +79,15 @@ static __device__ __forceinline__ int min16(const i32x16 &a)
     return min(min(mn, m4), a[15]);
 }
 
-// Chains of three-operand minima (v_min3): a two-operand float minimum of
-// raw accumulator values costs two canonicalising v_max first, which a
-// pairwise tree of eight values pays three times (11 vector ops, 6 as chains;
-// INT8: 5 and 4).
+// Chains of three-operand minima (v_min3 / v_minimum3): 4 vector ops for
+// eight values, where a pairwise tree takes 5 (INT8) or, with minNum's
+// canonicalising v_max on raw operands, 11 (float).
 static __device__ __forceinline__ float min8(const f32x8 &a)
 {
-    const float m0 = __builtin_fminf(__builtin_fminf(a[0], a[1]), a[2]);
-    const float m1 = __builtin_fminf(__builtin_fminf(a[3], a[4]), a[5]);
-    const float m2 = __builtin_fminf(__builtin_fminf(m0, a[6]), a[7]);
-    return __builtin_fminf(m2, m1);
+    const float m0 = fmin_acc(fmin_acc(a[0], a[1]), a[2]);
+    const float m1 = fmin_acc(fmin_acc(a[3], a[4]), a[5]);
+    const float m2 = fmin_acc(fmin_acc(m0, a[6]), a[7]);
+    return fmin_acc(m2, m1);
 }
 
 static __device__ __forceinline__ int min8(const i32x8 &a)
@@ -111,7 +118,7 @@ struct FloatKeys {
     static __device__ __forceinline__ float gate_min(const f32x16 &acc) { return min16(acc); }
     static __device__ __forceinline__ float group_min(const f32x16 &a, int g)
     {
-        return __builtin_fminf(__builtin_fminf(__builtin_fminf(a[4 * g], a[4 * g + 1]), a[4 * g + 2]), a[4 * g + 3]);
+        return fmin_acc(fmin_acc(fmin_acc(a[4 * g], a[4 * g + 1]), a[4 * g + 2]), a[4 * g + 3]);
     }
     static __device__ __forceinline__ float gate_thr(float thr) { return thr; }
     static __device__ __forceinline__ float key(const f32x16 &acc, int r, uint32_t, int) { return acc[r]; }
@@ -401,7 +408,7 @@ struct FloatQ : Base {
     static __device__ __forceinline__ float gate_min(const f32x8 &acc) { return min8(acc); }
     static __device__ __forceinline__ float group_min(const f32x8 &a, int g)
     {
-        return __builtin_fminf(__builtin_fminf(__builtin_fminf(a[4 * g], a[4 * g + 1]), a[4 * g + 2]), a[4 * g + 3]);
+        return fmin_acc(fmin_acc(fmin_acc(a[4 * g], a[4 * g + 1]), a[4 * g + 2]), a[4 * g + 3]);
     }
     static __device__ __forceinline__ float key(const f32x8 &acc, int r, uint32_t, int) { return acc[r]; }
 };
